@@ -1,0 +1,223 @@
+/*
+ * wd.h -- C ABI of the MI355X Wilson-Dirac solver library (libwdirac.so).
+ *
+ * The library applies the Wilson-Dirac operator of the paper "Towards
+ * Lattice Quantum Chromodynamics on FPGA devices" (Korcyl & Korcyl), Eq. (1)
+ * of Sec. 2.1, with the hopping term taken with a minus sign,
+ *
+ *   (D psi)(x) = psi(x) - kappa * sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                        + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ],
+ *
+ * gamma_mu as printed in the paper's Appendix A, and solves D x = b by
+ * conjugate gradient (Sec. 2.2) on the normal equations D^dag D x = D^dag b.
+ * Boundary conditions are periodic in x, y, z and (by default) antiperiodic
+ * in t: a hop across the t boundary is multiplied by -1 (Sec. 2.3 allows
+ * periodic or antiperiodic conditions).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Lattice extents dims[4] = {Lx, Ly, Lz, Lt}, each even and >= 2; V is
+ *   their product; V * nrhs must stay below 2^31 / 12.
+ * - Site index s = x + Lx*(y + Ly*(z + Lz*t)); direction mu = 0,1,2,3 =
+ *   x,y,z,t (the link arrays U_x..U_t of Sec. 6.2).
+ * - Canonical gauge field (caller-owned, DEVICE memory, float64):
+ *   U[s][mu][a][b][re,im], 72 doubles per site, U_mu(s) row-major (the
+ *   su3_matrix nesting of Sec. 6.1).  Links must be special unitary for the
+ *   12-real compressed forms (row 3 is rebuilt as conj(row1 x row2),
+ *   Sec. 6.1) to be exact.
+ * - Canonical spinor (caller-owned, DEVICE memory, float64):
+ *   psi[rhs][s][spin][colour][re,im], 24 doubles per site and right-hand
+ *   side (the su3_spinor nesting of Sec. 6.1).
+ * - Precision codes select the internal storage/compute format:
+ *   WD_F64 (float64 fields and links), WD_F32 (float32 spinors, 12-real
+ *   float32 links, float32 arithmetic), WD_F16 (binary16 spinors with a
+ *   float32 scale per site, 12-real binary16 links, float32 arithmetic).
+ *   Global sums are always accumulated in float64.
+ * - `stream` is a hipStream_t (NULL = the null stream).  Unless stated,
+ *   calls are stream-ordered and asynchronous with respect to the host.
+ * - Every function returns WD_OK (0), WD_PENDING (1) or a negative error
+ *   code; wd_last_error() returns a thread-local message for the last
+ *   error on the calling thread.  Arguments are validated before any GPU
+ *   work is issued; on error nothing is enqueued and outputs are untouched.
+ * - Pointers passed in are never freed or retained by the library, except
+ *   that b and x given to wd_submit must stay valid until wd_poll returns
+ *   something other than WD_PENDING for that ticket.
+ */
+#ifndef WD_H
+#define WD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wd_lattice wd_lattice; /* geometry + resident packed gauge forms */
+typedef struct wd_field wd_field;     /* a spinor field in the internal layout */
+typedef struct wd_server wd_server;   /* continuous-batching solve server */
+
+enum {
+    WD_OK = 0,
+    WD_PENDING = 1,
+    WD_ERR_ARG = -1,     /* invalid argument */
+    WD_ERR_NOMEM = -2,   /* device allocation failed or request exceeds the budget */
+    WD_ERR_HIP = -3,     /* a HIP runtime call failed */
+    WD_ERR_NOCONV = -4,  /* max_iter reached before the tolerance */
+    WD_ERR_NUMERIC = -5, /* NaN/Inf or a zero denominator inside the solve */
+    WD_ERR_NOGAUGE = -6, /* operator used before wd_set_gauge */
+    WD_ERR_NOTFOUND = -7,/* unknown ticket */
+    WD_ERR_STATE = -8    /* call not valid in the object's current state */
+};
+
+enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 };
+
+enum { WD_BC_ANTIPERIODIC_T = 1u << 0 };
+
+/* ---------------------------------------------------------------- lattice */
+
+/* Create a lattice of extents dims (each even, >= 2).  bc_flags:
+ * WD_BC_ANTIPERIODIC_T for antiperiodic t (else periodic everywhere).
+ * *out receives an opaque handle owned by the caller; free it with
+ * wd_destroy_lattice.  Allocates no device memory yet. */
+int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out);
+
+/* Free the lattice and its packed gauge forms.  WD_ERR_STATE if a server
+ * still holds requests on it. */
+int wd_destroy_lattice(wd_lattice *lat);
+
+/* Volume V of a lattice (host query). */
+int wd_lattice_volume(const wd_lattice *lat, int64_t *volume);
+
+/* Gauge ingest (Sec. 2.3: links are loaded once and stay resident).
+ * U: canonical float64 device array (72 doubles per site).  Packs the
+ * float64 18-real form now (the low-precision 12-real forms are derived
+ * from it on first use).  The library keeps its own copy; U may be freed
+ * after the stream reaches this point.  Synchronises `stream`. */
+int wd_set_gauge(wd_lattice *lat, const double *U, void *stream);
+
+/* Bytes of device memory the lattice's packed gauge forms use now. */
+int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes);
+
+/* ---------------------------------------------------------------- operator */
+
+/* out = D in (Eq. (1), minus sign) for one right-hand side, in and out
+ * canonical float64 device spinors of V*24 doubles (must not overlap).
+ * prec chooses the internal format; for WD_F32/WD_F16 the input is rounded
+ * to that format first and the result widened to float64. */
+int wd_apply_D(wd_lattice *lat, double kappa, int prec, const double *in, double *out,
+               void *stream);
+
+/* out = D^dag in.  D^dag = gamma5 D gamma5 (Sec. 2.2): D with the two spin
+ * projectors exchanged. */
+int wd_apply_Ddag(wd_lattice *lat, double kappa, int prec, const double *in, double *out,
+                  void *stream);
+
+/* Batched form: nrhs (1..12) canonical spinors stacked as [rhs][V][24]; each
+ * gauge link is loaded once per site for all right-hand sides. */
+int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, const double *in,
+             double *out, void *stream);
+
+/* --------------------------------------------------- fields (internal layout)
+ * A wd_field holds nrhs spinors in the site-major structure-of-arrays layout
+ * the kernels use: 12 planes (spin*3+colour) of complex numbers, each plane
+ * indexed by s*nrhs + rhs (plus one float32 scale plane for WD_F16).  Used to
+ * time the stencil on resident data and to chain operators without the
+ * canonical round trip. */
+int wd_field_create(wd_lattice *lat, int prec, int nrhs, wd_field **out);
+int wd_field_destroy(wd_field *f);
+/* canonical float64 [rhs][V][24] (device) -> field, rounding to its format */
+int wd_field_import(wd_field *f, const double *canon, void *stream);
+/* field -> canonical float64 [rhs][V][24] (device) */
+int wd_field_export(const wd_field *f, double *canon, void *stream);
+/* out = D in (dagger = 0) or D^dag in (dagger = 1) on fields of the same
+ * lattice, precision and nrhs; in and out must be different fields. */
+int wd_dslash(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_field *out,
+              void *stream);
+
+/* ---------------------------------------------------------------- solver */
+
+typedef struct {
+    double kappa;              /* hopping parameter */
+    double tol;                /* stop when ||r|| <= tol * ||D^dag b|| (normal equations) */
+    int32_t max_iter;          /* cap on CG iterations (inner iterations for mixed) */
+    int32_t prec_inner;        /* WD_F64: plain FP64 CG; WD_F32 / WD_F16: mixed precision */
+    int32_t nrhs;              /* 1..12 independent right-hand sides */
+    int32_t reliable_max_iter; /* mixed: FP64 reliable update at least this often (<= 0: 50) */
+    double reliable_delta;     /* mixed: update when ||r_lo|| < delta * max||r_lo|| (<= 0: 0.1) */
+    int32_t x0_given;          /* 1: x holds a starting guess on entry; 0: start from x = 0 */
+} wd_solve_params;
+
+typedef struct {
+    int32_t status;           /* WD_OK, WD_ERR_NOCONV or WD_ERR_NUMERIC for this rhs */
+    int32_t iters;            /* CG iterations (inner iterations for mixed) */
+    int32_t reliable_updates; /* FP64 true-residual recomputations (incl. the final check) */
+    double true_rel_resid;    /* ||D^dag b - D^dag D x|| / ||D^dag b|| in FP64 */
+    double rel_resid_D;       /* ||b - D x|| / ||b|| in FP64 */
+    double seconds;           /* wall time of the solve (submit to completion when served) */
+} wd_solve_info;
+
+/* Solve D^dag D x = D^dag b for nrhs right-hand sides (blocking; returns when
+ * x is written).  b, x: canonical float64 device spinors [nrhs][V][24].
+ * info: host array of nrhs entries.  Returns WD_OK if every rhs converged,
+ * else the first failing rhs's status; x always holds the last iterate.
+ * Mixed precision (prec_inner = WD_F32/WD_F16) runs the inner CG in that
+ * format on 12-real links and recomputes the residual in FP64 (reliable
+ * updates); the stopping test is always the FP64 true residual. */
+int wd_cg_solve(wd_lattice *lat, const wd_solve_params *p, const double *b, double *x,
+                wd_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct {
+    size_t hbm_budget_bytes; /* cap on solver workspace + gauge forms of live requests */
+    int32_t max_active;      /* requests iterating at once (<= 0: 8) */
+    int32_t chunk_iters;     /* CG iterations enqueued per request per scheduling turn (<= 0: auto) */
+} wd_server_config;
+
+/* Start a server with its own scheduler thread and one HIP stream per active
+ * slot.  Requests are admitted in arrival order while the HBM budget and the
+ * slot count allow; admitted requests iterate concurrently on their streams
+ * and retire independently (continuous batching). */
+int wd_server_create(const wd_server_config *cfg, wd_server **out);
+
+/* Queue a solve (non-blocking).  Same arguments as wd_cg_solve; the lattice
+ * must have its gauge set and must outlive the request.  *ticket identifies
+ * it.  WD_ERR_NOMEM if the request alone exceeds the whole budget. */
+int wd_submit(wd_server *s, wd_lattice *lat, const wd_solve_params *p, const double *b,
+              double *x, uint64_t *ticket);
+
+/* WD_PENDING while queued or running; otherwise the solve's return code, with
+ * info (host, nrhs entries) filled in.  A finished ticket may be polled again
+ * until wd_server_destroy. */
+int wd_poll(wd_server *s, uint64_t ticket, wd_solve_info *info);
+
+/* Completed solves per second since the server started, and the 50th/99th
+ * percentile (nearest rank) of completion - submission latency, seconds. */
+int wd_server_stats(wd_server *s, double *solves_per_s, double *p50_s, double *p99_s);
+
+/* Peak bytes the server had admitted at once (workspace + gauge forms). */
+int wd_server_peak_bytes(wd_server *s, size_t *bytes);
+
+/* Drain every queued and running request, then free the server. */
+int wd_server_destroy(wd_server *s);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Thread-local text of the last error on this thread (library-owned, valid
+ * until the next call on this thread). */
+const char *wd_last_error(void);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * stencil launch.  wd_timing_read returns the summed milliseconds and launch
+ * count for one kernel family ("dslash_f64", "dslash_f32", "dslash_f16")
+ * since the last reset; it synchronises the pending events. */
+int wd_timing_enable(int on);
+int wd_timing_reset(void);
+int wd_timing_read(const char *name, double *total_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WD_H */

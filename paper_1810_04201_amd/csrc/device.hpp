@@ -1,0 +1,354 @@
+// Device-side building blocks: complex arithmetic, field and link accessors
+// for the three storage formats, and the deterministic block reduction with
+// its solver-state finaliser.
+#pragma once
+
+#include "wd_internal.hpp"
+
+namespace wd {
+
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> scale(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+// i * a
+template <typename R>
+__device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+// a * b
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a * b
+template <typename R>
+__device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> acc) {
+    return {acc.re + a.re * b.re - a.im * b.im, acc.im + a.re * b.im + a.im * b.re};
+}
+// acc + conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cfmac(cx<R> a, cx<R> b, cx<R> acc) {
+    return {acc.re + a.re * b.re + a.im * b.im, acc.im + a.re * b.im - a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ spinors
+
+template <int PREC>
+struct Spinor;
+
+template <>
+struct Spinor<WD_F64> {
+    using R = double;
+    static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
+        const double2 *p = (const double2 *)f.data;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            double2 d = p[(size_t)k * f.n + i];
+            v[k] = {d.x, d.y};
+        }
+    }
+    static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
+        double2 *p = (double2 *)f.data;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[(size_t)k * f.n + i] = make_double2(v[k].re, v[k].im);
+    }
+};
+
+template <>
+struct Spinor<WD_F32> {
+    using R = float;
+    static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
+        const float4 *p = (const float4 *)f.data;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            float4 q = p[(size_t)j * f.n + i];
+            v[2 * j] = {q.x, q.y};
+            v[2 * j + 1] = {q.z, q.w};
+        }
+    }
+    static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
+        float4 *p = (float4 *)f.data;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            p[(size_t)j * f.n + i] =
+                make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
+    }
+};
+
+template <>
+struct Spinor<WD_F16> {
+    using R = float;
+    static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
+        const h8_t *p = (const h8_t *)f.data;
+        const float s = f.scale[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            h8_t q = p[(size_t)j * f.n + i];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                v[4 * j + m] = {s * (float)q[2 * m], s * (float)q[2 * m + 1]};
+        }
+    }
+    static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
+        float mx = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) mx = fmaxf(mx, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float inv = mx > 0.f ? 1.0f / mx : 0.f;
+        h8_t *p = (h8_t *)f.data;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            h8_t q;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                q[2 * m] = (_Float16)(v[4 * j + m].re * inv);
+                q[2 * m + 1] = (_Float16)(v[4 * j + m].im * inv);
+            }
+            p[(size_t)j * f.n + i] = q;
+        }
+        f.scale[i] = mx;
+    }
+};
+
+// ------------------------------------------------------------------ links
+
+// row 2 of a special unitary matrix from rows 0 and 1: conj(row0 x row1)
+template <typename R>
+__device__ __forceinline__ void reconstruct_row2(cx<R> u[9]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        cx<R> c = cmul(u[j1], u[3 + j2]) - cmul(u[j2], u[3 + j1]);
+        u[6 + j] = conj(c);
+    }
+}
+
+template <int PREC>
+struct Link;
+
+template <>
+struct Link<WD_F64> {
+    using R = double;
+    static __device__ __forceinline__ void load(const void *g, int V, int mu, int s, cx<R> u[9]) {
+        const double2 *p = (const double2 *)g + (size_t)mu * 9 * V;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double2 d = p[(size_t)k * V + s];
+            u[k] = {d.x, d.y};
+        }
+    }
+};
+
+template <>
+struct Link<WD_F32> {
+    using R = float;
+    static __device__ __forceinline__ void load(const void *g, int V, int mu, int s, cx<R> u[9]) {
+        const float4 *p = (const float4 *)g + (size_t)mu * 3 * V;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            float4 q = p[(size_t)j * V + s];
+            u[2 * j] = {q.x, q.y};
+            u[2 * j + 1] = {q.z, q.w};
+        }
+        reconstruct_row2(u);
+    }
+};
+
+template <>
+struct Link<WD_F16> {
+    using R = float;
+    static __device__ __forceinline__ void load(const void *g, int V, int mu, int s, cx<R> u[9]) {
+        const h4_t *p = (const h4_t *)g + (size_t)mu * 3 * V;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            h4_t q = p[(size_t)j * V + s];
+            u[2 * j] = {(float)q[0], (float)q[1]};
+            u[2 * j + 1] = {(float)q[2], (float)q[3]};
+        }
+        reconstruct_row2(u);
+    }
+};
+
+// ------------------------------------------------------------------ reduction
+//
+// Deterministic: a fixed butterfly inside each wave (nrhs == 1) or a fixed
+// LDS tree over site slots (nrhs > 1), one partial per block and rhs, and
+// the last block to arrive (atomic ticket) sums the partials in a fixed
+// order and runs the finaliser.  Results are bitwise reproducible for a
+// given launch shape, independent of block scheduling.
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+__device__ inline void finalize_rhs(const RedArgs &red, int r, double total) {
+    RhsState &st = red.st[r];
+    const SolveCtl &c = red.ctl;
+    switch (red.mode) {
+        case RED_ALPHA:
+            if (st.active) {
+                st.tt = total;
+                if (!(total > 0.0) || !finite(total)) {
+                    st.failed = WD_ERR_NUMERIC;
+                    st.active = 0;
+                    st.alpha = 0.0;
+                } else {
+                    st.alpha = st.rr / total;
+                }
+            }
+            break;
+        case RED_RR:
+            if (st.active) {
+                st.iters += 1;
+                st.since += 1;
+                st.rr_prev = st.rr;
+                st.rr = total;
+                if (!finite(total)) {
+                    st.failed = WD_ERR_NUMERIC;
+                    st.active = 0;
+                    break;
+                }
+                st.beta = total / st.rr_prev;
+                if (total > st.rr_max) st.rr_max = total;
+                bool trig = total <= c.tol2 * st.rr0;
+                if (c.mixed && total < c.delta2 * st.rr_max) trig = true;
+                if (c.max_inner > 0 && st.since >= c.max_inner) trig = true;
+                if (st.iters >= c.max_iter) {
+                    st.failed = WD_ERR_NOCONV;
+                    trig = true;
+                }
+                if (trig) {
+                    st.active = 0;
+                    st.trigger = 1;
+                }
+            }
+            break;
+        case RED_TRUE:
+            if (!st.converged && st.trigger) {
+                st.rr_true = total;
+                st.updates += 1;
+                st.trigger = 0;
+                if (!finite(total)) {
+                    st.failed = WD_ERR_NUMERIC;
+                    st.active = 0;
+                } else if (total <= c.tol2 * st.rr0) {
+                    st.converged = 1;
+                    st.failed = 0;
+                    st.active = 0;
+                } else if (st.failed) {
+                    st.active = 0;
+                } else {
+                    st.beta = (st.updates == 1) ? 0.0 : total / st.rr_prev;
+                    st.rr = total;
+                    st.rr_max = total;
+                    st.since = 0;
+                    st.active = 1;
+                }
+            }
+            break;
+        case RED_B0:
+            st.rr0 = total;
+            st.active = 0;
+            st.converged = 0;
+            st.failed = 0;
+            st.trigger = 0;
+            if (!finite(total)) {
+                st.failed = WD_ERR_NUMERIC;
+            } else if (total == 0.0) {
+                st.converged = 1;  // b' = 0: x = 0 is exact
+            } else {
+                st.trigger = 1;    // the first reliable update forms r and p
+            }
+            break;
+        case RED_AUX: st.aux = total; break;
+        case RED_AUX2: st.aux2 = total; break;
+        default: break;
+    }
+}
+
+__device__ inline void recount_batch(const RedArgs &red) {
+    int na = 0, nt = 0, nd = 0;
+    for (int r = 0; r < red.ctl.nrhs; ++r) {
+        const RhsState &st = red.st[r];
+        na += st.active;
+        nt += st.trigger;
+        nd += (st.converged || (st.failed && !st.trigger)) ? 1 : 0;
+    }
+    red.batch->n_active = na;
+    red.batch->n_trigger = nt;
+    red.batch->n_done = nd;
+}
+
+// v: this thread's contribution (0 for idle threads).  Must be reached by
+// every thread of every block of the launch.  blockDim.x = S * nrhs with S a
+// power of two and the block's first entry a multiple of nrhs, so thread t
+// belongs to rhs t % nrhs.
+__device__ inline void reduce_finalize(double v, const RedArgs &red, int nrhs) {
+    __shared__ double sm[1024];
+    __shared__ int am_last;
+    const int tid = threadIdx.x;
+    const int bd = blockDim.x;
+    const int S = bd / nrhs;
+    if (nrhs == 1) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) == 0) sm[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < (bd >> 6); ++w) s += sm[w];
+            red.partials[blockIdx.x] = s;
+        }
+    } else {
+        sm[tid] = v;
+        __syncthreads();
+        for (int stride = S >> 1; stride > 0; stride >>= 1) {
+            if (tid < stride * nrhs) sm[tid] += sm[tid + stride * nrhs];
+            __syncthreads();
+        }
+        if (tid < nrhs) red.partials[(size_t)blockIdx.x * nrhs + tid] = sm[tid];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        unsigned prev = atomicAdd(red.ticket, 1u);
+        am_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!am_last) return;
+    __threadfence();
+    const int nb = gridDim.x;
+    const int slot = tid / nrhs;
+    const int r = tid - slot * nrhs;
+    double acc = 0.0;
+    const volatile double *part = red.partials;
+    for (int b = slot; b < nb; b += S) acc += part[(size_t)b * nrhs + r];
+    sm[tid] = acc;
+    __syncthreads();
+    for (int stride = S >> 1; stride > 0; stride >>= 1) {
+        if (tid < stride * nrhs) sm[tid] += sm[tid + stride * nrhs];
+        __syncthreads();
+    }
+    if (tid < nrhs && red.mode != RED_NONE) finalize_rhs(red, tid, sm[tid]);
+    __syncthreads();
+    if (tid == 0) {
+        if (red.mode != RED_NONE) recount_batch(red);
+        *red.ticket = 0u;
+        __threadfence();
+    }
+}
+
+}  // namespace wd

@@ -1,0 +1,347 @@
+// C ABI: lattices, gauge ingest, fields, operator application, errors and
+// stencil timing.  The solver is in solver.cpp and the server in server.cpp.
+#include "runtime.hpp"
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <map>
+
+namespace wd {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+double now_seconds() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+bool valid_prec(int p) { return p == WD_F64 || p == WD_F32 || p == WD_F16; }
+
+FieldRef carve(char *&cursor, int prec, int nrhs, int V) {
+    FieldRef f{};
+    f.prec = prec;
+    f.nrhs = nrhs;
+    f.n = V * nrhs;
+    f.data = cursor;
+    cursor += (size_t)planes_for(prec) * 16u * (size_t)f.n;
+    if (prec == WD_F16) {
+        f.scale = (float *)cursor;
+        cursor += ((4u * (size_t)f.n + 255u) / 256u) * 256u;
+    }
+    return f;
+}
+
+void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err) {
+    std::lock_guard<std::mutex> lk(lat->mu);
+    if (!lat->has_gauge) {
+        *err = fail(WD_ERR_NOGAUGE, "gauge field not set (call wd_set_gauge first)");
+        return nullptr;
+    }
+    if (lat->gauge[prec]) return lat->gauge[prec];
+    void *p = nullptr;
+    if (hipMalloc(&p, gauge_bytes(prec, lat->g.V)) != hipSuccess) {
+        *err = fail(WD_ERR_NOMEM, "hipMalloc of the %s gauge form failed",
+                    prec == WD_F32 ? "F32-12" : "F16-12");
+        return nullptr;
+    }
+    launch_gauge_lo(lat->gauge[WD_F64], p, prec, lat->g.V, s);
+    // other streams (server slots) may use the form next: finish building it
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipFree(p);
+        *err = fail(WD_ERR_HIP, "building the low-precision gauge form failed");
+        return nullptr;
+    }
+    lat->gauge[prec] = p;
+    return p;
+}
+
+// ------------------------------------------------------------------ timing
+
+struct TimingRec {
+    double ms = 0.0;
+    int64_t count = 0;
+};
+struct PendingTime {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::mutex g_tmu;
+static std::atomic<int> g_timing{0};
+static std::map<std::string, TimingRec> g_times;
+static std::vector<PendingTime> g_pending;
+static std::vector<hipEvent_t> g_evpool;
+
+static hipEvent_t take_event() {
+    if (!g_evpool.empty()) {
+        hipEvent_t e = g_evpool.back();
+        g_evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+static void drain_pending_locked() {
+    for (auto &p : g_pending) {
+        (void)hipEventSynchronize(p.b);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto &r = g_times[p.name];
+            r.ms += ms;
+            r.count += 1;
+        }
+        g_evpool.push_back(p.a);
+        g_evpool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
+void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
+            const FieldRef &out, const RedArgs *red, Gate gate, hipStream_t s) {
+    if (!g_timing.load(std::memory_order_relaxed)) {
+        launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s);
+        return;
+    }
+    static const char *names[3] = {"dslash_f64", "dslash_f32", "dslash_f16"};
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        if (g_pending.size() > 4096) drain_pending_locked();
+        a = take_event();
+        b = take_event();
+    }
+    (void)hipEventRecord(a, s);
+    launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s);
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back({names[in.prec], a, b});
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char *wd_last_error(void) { return g_err.c_str(); }
+
+int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out) {
+    if (!dims || !out) return fail(WD_ERR_ARG, "null argument");
+    int64_t V = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (dims[m] < 2 || (dims[m] & 1))
+            return fail(WD_ERR_ARG, "dims[%d] = %d: every extent must be even and >= 2", m,
+                        (int)dims[m]);
+        V *= dims[m];
+    }
+    if (V * 12 * 12 >= (int64_t)1 << 31)
+        return fail(WD_ERR_ARG, "volume %lld too large (V * 12 rhs * 12 must be < 2^31)",
+                    (long long)V);
+    if (bc_flags & ~(uint32_t)WD_BC_ANTIPERIODIC_T)
+        return fail(WD_ERR_ARG, "unknown boundary flags 0x%x", bc_flags);
+    wd_lattice *lat = new (std::nothrow) wd_lattice();
+    if (!lat) return fail(WD_ERR_NOMEM, "host allocation failed");
+    for (int m = 0; m < 4; ++m) lat->g.L[m] = dims[m];
+    lat->g.V = (int)V;
+    lat->g.antiperiodic = (bc_flags & WD_BC_ANTIPERIODIC_T) ? 1 : 0;
+    *out = lat;
+    return WD_OK;
+}
+
+int wd_destroy_lattice(wd_lattice *lat) {
+    if (!lat) return fail(WD_ERR_ARG, "null lattice");
+    if (lat->users.load() != 0)
+        return fail(WD_ERR_STATE, "lattice still has %d requests on a server", lat->users.load());
+    for (int p = 0; p < 3; ++p)
+        if (lat->gauge[p]) (void)hipFree(lat->gauge[p]);
+    delete lat;
+    return WD_OK;
+}
+
+int wd_lattice_volume(const wd_lattice *lat, int64_t *volume) {
+    if (!lat || !volume) return fail(WD_ERR_ARG, "null argument");
+    *volume = lat->g.V;
+    return WD_OK;
+}
+
+int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes) {
+    if (!lat || !bytes) return fail(WD_ERR_ARG, "null argument");
+    size_t b = 0;
+    for (int p = 0; p < 3; ++p)
+        if (lat->gauge[p]) b += gauge_bytes(p, lat->g.V);
+    *bytes = b;
+    return WD_OK;
+}
+
+int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
+    if (!lat || !U) return fail(WD_ERR_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(lat->mu);
+    if (lat->users.load() != 0)
+        return fail(WD_ERR_STATE, "gauge cannot change while requests are in flight");
+    if (!lat->gauge[WD_F64]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, gauge_bytes(WD_F64, lat->g.V)) != hipSuccess)
+            return fail(WD_ERR_NOMEM, "hipMalloc of the F64 gauge form failed");
+        lat->gauge[WD_F64] = p;
+    }
+    launch_pack_gauge_f64(U, lat->gauge[WD_F64], lat->g.V, s);
+    for (int p = 1; p < 3; ++p)
+        if (lat->gauge[p]) launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], p, lat->g.V, s);
+    WD_HIP_CHECK(hipGetLastError());
+    WD_HIP_CHECK(hipStreamSynchronize(s));
+    lat->has_gauge = true;
+    return WD_OK;
+}
+
+int wd_field_create(wd_lattice *lat, int prec, int nrhs, wd_field **out) {
+    if (!lat || !out) return fail(WD_ERR_ARG, "null argument");
+    if (!valid_prec(prec)) return fail(WD_ERR_ARG, "unknown precision %d", prec);
+    if (nrhs < 1 || nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", nrhs);
+    wd_field *f = new (std::nothrow) wd_field();
+    if (!f) return fail(WD_ERR_NOMEM, "host allocation failed");
+    size_t bytes = spinor_bytes(prec, (int64_t)lat->g.V * nrhs) + 256;
+    if (hipMalloc(&f->mem, bytes) != hipSuccess) {
+        delete f;
+        return fail(WD_ERR_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    char *cur = (char *)f->mem;
+    f->ref = carve(cur, prec, nrhs, lat->g.V);
+    f->lat = lat;
+    f->prec = prec;
+    f->nrhs = nrhs;
+    *out = f;
+    return WD_OK;
+}
+
+int wd_field_destroy(wd_field *f) {
+    if (!f) return fail(WD_ERR_ARG, "null field");
+    (void)hipFree(f->mem);
+    delete f;
+    return WD_OK;
+}
+
+int wd_field_import(wd_field *f, const double *canon, void *stream) {
+    if (!f || !canon) return fail(WD_ERR_ARG, "null argument");
+    launch_import(canon, f->ref, (hipStream_t)stream);
+    WD_HIP_CHECK(hipGetLastError());
+    return WD_OK;
+}
+
+int wd_field_export(const wd_field *f, double *canon, void *stream) {
+    if (!f || !canon) return fail(WD_ERR_ARG, "null argument");
+    launch_export(f->ref, canon, (hipStream_t)stream);
+    WD_HIP_CHECK(hipGetLastError());
+    return WD_OK;
+}
+
+int wd_dslash(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_field *out,
+              void *stream) {
+    if (!lat || !in || !out) return fail(WD_ERR_ARG, "null argument");
+    if (in == out) return fail(WD_ERR_ARG, "in and out must be different fields");
+    if (in->lat != lat || out->lat != lat) return fail(WD_ERR_ARG, "fields of another lattice");
+    if (in->prec != out->prec || in->nrhs != out->nrhs)
+        return fail(WD_ERR_ARG, "in/out precision or nrhs differ");
+    if (!std::isfinite(kappa)) return fail(WD_ERR_ARG, "kappa not finite");
+    if (dagger != 0 && dagger != 1) return fail(WD_ERR_ARG, "dagger must be 0 or 1");
+    int err = WD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    void *g = gauge_for(lat, in->prec, s, &err);
+    if (!g) return err;
+    dslash(lat, g, kappa, dagger, in->ref, out->ref, nullptr, Gate{nullptr, nullptr}, s);
+    WD_HIP_CHECK(hipGetLastError());
+    return WD_OK;
+}
+
+int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, const double *in,
+             double *out, void *stream) {
+    if (!lat || !in || !out) return fail(WD_ERR_ARG, "null argument");
+    if (!valid_prec(prec)) return fail(WD_ERR_ARG, "unknown precision %d", prec);
+    if (nrhs < 1 || nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", nrhs);
+    if (!std::isfinite(kappa)) return fail(WD_ERR_ARG, "kappa not finite");
+    if (dagger != 0 && dagger != 1) return fail(WD_ERR_ARG, "dagger must be 0 or 1");
+    if (in == out) return fail(WD_ERR_ARG, "in and out must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    int err = WD_OK;
+    void *g = gauge_for(lat, prec, s, &err);
+    if (!g) return err;
+    const int V = lat->g.V;
+    size_t one = spinor_bytes(prec, (int64_t)V * nrhs) + 256;
+    void *mem = nullptr;
+    if (hipMallocAsync(&mem, 2 * one, s) != hipSuccess)
+        return fail(WD_ERR_NOMEM, "workspace allocation of %zu bytes failed", 2 * one);
+    char *cur = (char *)mem;
+    FieldRef a = carve(cur, prec, nrhs, V);
+    cur = (char *)mem + one;
+    FieldRef b = carve(cur, prec, nrhs, V);
+    launch_import(in, a, s);
+    dslash(lat, g, kappa, dagger, a, b, nullptr, Gate{nullptr, nullptr}, s);
+    launch_export(b, out, s);
+    (void)hipFreeAsync(mem, s);
+    WD_HIP_CHECK(hipGetLastError());
+    return WD_OK;
+}
+
+int wd_apply_D(wd_lattice *lat, double kappa, int prec, const double *in, double *out,
+               void *stream) {
+    return wd_apply(lat, kappa, prec, 0, 1, in, out, stream);
+}
+
+int wd_apply_Ddag(wd_lattice *lat, double kappa, int prec, const double *in, double *out,
+                  void *stream) {
+    return wd_apply(lat, kappa, prec, 1, 1, in, out, stream);
+}
+
+int wd_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing.store(on ? 1 : 0);
+    return WD_OK;
+}
+
+int wd_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    drain_pending_locked();
+    g_times.clear();
+    return WD_OK;
+}
+
+int wd_timing_read(const char *name, double *total_ms, int64_t *count) {
+    if (!name || !total_ms || !count) return fail(WD_ERR_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    drain_pending_locked();
+    auto it = g_times.find(name);
+    if (it == g_times.end()) {
+        *total_ms = 0.0;
+        *count = 0;
+    } else {
+        *total_ms = it->second.ms;
+        *count = it->second.count;
+    }
+    return WD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Host-side runtime objects behind the C ABI: lattices with their resident
+// gauge forms, spinor fields, the CG solve state machine and the server.
+#pragma once
+
+#include <atomic>
+#include <cstdio>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "wd_internal.hpp"
+
+struct wd_lattice {
+    wd::Geom g{};
+    void *gauge[3] = {nullptr, nullptr, nullptr};  // F64-18, F32-12, F16-12
+    bool has_gauge = false;
+    std::mutex mu;
+    std::atomic<int> users{0};  // requests in flight on a server
+};
+
+struct wd_field {
+    wd_lattice *lat = nullptr;
+    int prec = WD_F64;
+    int nrhs = 1;
+    void *mem = nullptr;
+    wd::FieldRef ref{};
+};
+
+namespace wd {
+
+void set_error(const char *fmt, ...);
+int fail(int code, const char *fmt, ...);
+#define WD_HIP_CHECK(call)                                                               \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::wd::fail(WD_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool valid_prec(int p);
+// packed gauge form for a precision, building the 12-real forms on first use
+// (enqueued on stream s).  Returns nullptr and sets the error on failure.
+void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err);
+
+// stencil launch with optional event timing
+void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
+            const FieldRef &out, const RedArgs *red, Gate gate, hipStream_t s);
+
+FieldRef carve(char *&cursor, int prec, int nrhs, int V);
+
+// ------------------------------------------------------------------ solve
+
+class Solve {
+  public:
+    Solve(wd_lattice *lat, const wd_solve_params &p, const double *b, double *x);
+    ~Solve();
+    static int validate(wd_lattice *lat, const wd_solve_params *p);
+    static size_t footprint(const wd_lattice *lat, const wd_solve_params &p);
+    // allocate device and pinned memory and bind a stream; no work enqueued
+    int setup(hipStream_t stream);
+    // enqueue the start sequence (source prep and first residual)
+    int start();
+    // advance the state machine; block: wait for device status.  Returns
+    // 1 when the solve has finished (info valid), 0 if still running, <0 error
+    int advance(bool block);
+    void info(wd_solve_info *out) const;
+    int result() const { return result_; }
+    size_t bytes() const { return bytes_; }
+    int nrhs() const { return p_.nrhs; }
+    double seconds = 0.0;
+
+  private:
+    struct Pending {
+        hipEvent_t ev;
+        int slot;
+        int epoch;
+    };
+    void enqueue_inner(int iters);
+    void enqueue_reliable(bool first);
+    void enqueue_finish();
+    int push_status();
+    RedArgs red(int mode) const;
+    Gate gate() const { return Gate{st_, batch_}; }
+
+    wd_lattice *lat_;
+    wd_solve_params p_;
+    const double *b_;
+    double *x_;
+    hipStream_t s_ = nullptr;
+    int prec_;
+    int chunk_ = 8;
+    void *gauge64_ = nullptr, *gauge_lo_ = nullptr;
+    void *mem_ = nullptr;
+    size_t bytes_ = 0;
+    FieldRef b64_{}, bp_{}, x64_{}, r64_{}, t64_{}, ax64_{};
+    FieldRef xl_{}, rl_{}, pl_{}, tl_{}, apl_{};
+    RhsState *st_ = nullptr;
+    BatchState *batch_ = nullptr;
+    unsigned *ticket_ = nullptr;
+    double *partials_ = nullptr;
+    SolveCtl ctl_{};
+    // pinned status ring
+    static constexpr int kSlots = 6;
+    RhsState *h_st_ = nullptr;      // kSlots * nrhs
+    BatchState *h_batch_ = nullptr; // kSlots
+    std::vector<hipEvent_t> events_;
+    std::deque<Pending> pending_;
+    int next_slot_ = 0;
+    int epoch_ = 0;
+    int phase_ = 0;  // 0 running, 1 finishing, 2 done
+    hipEvent_t final_ev_ = nullptr;
+    int final_slot_ = -1;
+    int result_ = WD_OK;
+};
+
+double now_seconds();
+
+}  // namespace wd

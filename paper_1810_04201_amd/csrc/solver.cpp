@@ -1,0 +1,314 @@
+// Conjugate gradient on the normal equations (Sec. 2.2) as a resumable,
+// stream-ordered state machine.
+//
+// Per inner iteration four kernels run back to back on the solve's stream:
+//   t  = D p         (stencil, fused |t|^2 -> alpha = |r|^2 / |t|^2)
+//   Ap = D^dag t     (stencil)
+//   x += alpha p, r -= alpha Ap  (fused |r|^2 -> beta, convergence, triggers)
+//   p  = r + beta p
+// All scalars stay on the device (RhsState); the host only reads a small
+// status record every `chunk_` iterations and never stalls the stream on it:
+// inner iterations enqueued after an rhs froze are exact no-ops, so results
+// do not depend on host timing.
+//
+// A reliable update (Sleijpen and van der Vorst) recomputes the residual in
+// float64: x64 += x_lo, r64 = D^dag b - D^dag D x64, and resumes the
+// recursion from r64 with beta = |r64|^2 / |r_prev|^2.  It runs once at the
+// start (forming r and p), whenever every unfinished rhs is frozen, and is
+// the final stopping test: an rhs converges only when its float64 true
+// residual meets the tolerance.  Plain FP64 CG triggers it only at the
+// convergence estimate; mixed precision also every `reliable_max_iter`
+// iterations and when |r_lo| drops below delta * max |r_lo|.
+#include <cmath>
+#include <cstring>
+
+#include "runtime.hpp"
+
+namespace wd {
+
+Solve::Solve(wd_lattice *lat, const wd_solve_params &p, const double *b, double *x)
+    : lat_(lat), p_(p), b_(b), x_(x), prec_(p.prec_inner) {}
+
+Solve::~Solve() {
+    for (auto e : events_) (void)hipEventDestroy(e);
+    if (final_ev_) (void)hipEventDestroy(final_ev_);
+    if (mem_) (void)hipFree(mem_);
+    if (h_st_) (void)hipHostFree(h_st_);
+    if (h_batch_) (void)hipHostFree(h_batch_);
+}
+
+int Solve::validate(wd_lattice *lat, const wd_solve_params *p) {
+    if (!lat || !p) return fail(WD_ERR_ARG, "null argument");
+    if (!std::isfinite(p->kappa)) return fail(WD_ERR_ARG, "kappa not finite");
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(WD_ERR_ARG, "tol must be > 0");
+    if (p->max_iter < 1) return fail(WD_ERR_ARG, "max_iter must be >= 1");
+    if (!valid_prec(p->prec_inner)) return fail(WD_ERR_ARG, "unknown precision %d", p->prec_inner);
+    if (p->nrhs < 1 || p->nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", p->nrhs);
+    if (p->x0_given != 0 && p->x0_given != 1) return fail(WD_ERR_ARG, "x0_given must be 0 or 1");
+    if (!lat->has_gauge) return fail(WD_ERR_NOGAUGE, "gauge field not set");
+    return WD_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255u) & ~(size_t)255u; }
+
+static size_t field_bytes(int prec, int64_t n) { return align256(spinor_bytes(prec, n)) + 256; }
+
+size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
+    const int64_t n = (int64_t)lat->g.V * p.nrhs;
+    const int lo = p.prec_inner;
+    const int lo_xr = lo == WD_F16 ? WD_F32 : lo;
+    size_t b = 6 * field_bytes(WD_F64, n);
+    b += 2 * field_bytes(lo_xr, n) + 3 * field_bytes(lo, n);
+    const int bs = block_for_nrhs(p.nrhs);
+    b += align256((size_t)(blocks_for(n, bs) + 1) * p.nrhs * sizeof(double));
+    b += align256(sizeof(RhsState) * 12) + 2 * 256;
+    return b;
+}
+
+int Solve::setup(hipStream_t stream) {
+    s_ = stream;
+    const int V = lat_->g.V;
+    const int nrhs = p_.nrhs;
+    const int64_t n = (int64_t)V * nrhs;
+    int err = WD_OK;
+    gauge64_ = gauge_for(lat_, WD_F64, s_, &err);
+    if (!gauge64_) return err;
+    if (prec_ != WD_F64) {
+        gauge_lo_ = gauge_for(lat_, prec_, s_, &err);
+        if (!gauge_lo_) return err;
+    } else {
+        gauge_lo_ = gauge64_;
+    }
+    bytes_ = footprint(lat_, p_);
+    if (hipMalloc(&mem_, bytes_) != hipSuccess) {
+        mem_ = nullptr;
+        return fail(WD_ERR_NOMEM, "hipMalloc of %zu bytes of solver workspace failed", bytes_);
+    }
+    char *base = (char *)mem_;
+    char *cur = base;
+    auto next = [&](int prec) {
+        char *c = cur;
+        FieldRef f = carve(c, prec, nrhs, V);
+        cur += field_bytes(prec, n);
+        return f;
+    };
+    b64_ = next(WD_F64);
+    bp_ = next(WD_F64);
+    x64_ = next(WD_F64);
+    r64_ = next(WD_F64);
+    t64_ = next(WD_F64);
+    ax64_ = next(WD_F64);
+    const int lo_xr = prec_ == WD_F16 ? WD_F32 : prec_;
+    xl_ = next(lo_xr);
+    rl_ = next(lo_xr);
+    pl_ = next(prec_);
+    tl_ = next(prec_);
+    apl_ = next(prec_);
+    const int bs = block_for_nrhs(nrhs);
+    partials_ = (double *)cur;
+    cur += align256((size_t)(blocks_for(n, bs) + 1) * nrhs * sizeof(double));
+    st_ = (RhsState *)cur;
+    cur += align256(sizeof(RhsState) * 12);
+    batch_ = (BatchState *)cur;
+    cur += 256;
+    ticket_ = (unsigned *)cur;
+    cur += 256;
+    if ((size_t)(cur - base) > bytes_) return fail(WD_ERR_STATE, "workspace layout overflow");
+
+    if (hipHostMalloc((void **)&h_st_, sizeof(RhsState) * kSlots * nrhs) != hipSuccess ||
+        hipHostMalloc((void **)&h_batch_, sizeof(BatchState) * kSlots) != hipSuccess)
+        return fail(WD_ERR_NOMEM, "pinned host allocation failed");
+    events_.resize(kSlots);
+    for (int i = 0; i < kSlots; ++i)
+        if (hipEventCreateWithFlags(&events_[i], hipEventDisableTiming) != hipSuccess)
+            return fail(WD_ERR_HIP, "hipEventCreate failed");
+    if (hipEventCreateWithFlags(&final_ev_, hipEventDisableTiming) != hipSuccess)
+        return fail(WD_ERR_HIP, "hipEventCreate failed");
+
+    ctl_.tol2 = p_.tol * p_.tol;
+    const double delta = p_.reliable_delta > 0 ? p_.reliable_delta : 0.1;
+    ctl_.delta2 = delta * delta;
+    ctl_.max_iter = p_.max_iter;
+    ctl_.nrhs = nrhs;
+    ctl_.mixed = prec_ != WD_F64;
+    ctl_.max_inner = ctl_.mixed ? (p_.reliable_max_iter > 0 ? p_.reliable_max_iter : 50) : 0;
+    // iterations per status read: large lattices need few, tiny ones many
+    const double site_iters = 4.0e7 / (double)n;
+    chunk_ = site_iters < 4 ? 4 : (site_iters > 64 ? 64 : (int)site_iters);
+    return WD_OK;
+}
+
+RedArgs Solve::red(int mode) const {
+    RedArgs r{};
+    r.partials = partials_;
+    r.ticket = ticket_;
+    r.st = st_;
+    r.batch = batch_;
+    r.ctl = ctl_;
+    r.mode = mode;
+    return r;
+}
+
+int Solve::start() {
+    const double k = p_.kappa;
+    const Gate none{nullptr, nullptr};
+    launch_init_state(st_, batch_, ticket_, p_.nrhs, s_);
+    launch_import(b_, b64_, s_);
+    RedArgs rb = red(RED_B0);
+    dslash(lat_, gauge64_, k, 1, b64_, bp_, &rb, none, s_);  // b' = D^dag b, |b'|^2
+    if (p_.x0_given)
+        launch_import(x_, x64_, s_);
+    else
+        launch_zero(x64_, s_);
+    launch_zero(xl_, s_);
+    enqueue_reliable(true);
+    if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "kernel launch failed");
+    return push_status();
+}
+
+void Solve::enqueue_inner(int iters) {
+    const double k = p_.kappa;
+    const Gate g = gate();
+    RedArgs ra = red(RED_ALPHA);
+    RedArgs rr = red(RED_RR);
+    for (int i = 0; i < iters; ++i) {
+        dslash(lat_, gauge_lo_, k, 0, pl_, tl_, &ra, g, s_);
+        dslash(lat_, gauge_lo_, k, 1, tl_, apl_, nullptr, g, s_);
+        launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
+        launch_update_p(pl_, rl_, g, s_);
+    }
+}
+
+void Solve::enqueue_reliable(bool first) {
+    const double k = p_.kappa;
+    const Gate none{nullptr, nullptr};
+    RedArgs rt = red(RED_TRUE);
+    if (first && !p_.x0_given) {
+        launch_residual(r64_, bp_, FieldRef{}, rt, s_);  // x = 0: r = b'
+    } else {
+        launch_accum_zero(x64_, xl_, st_, s_);
+        dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, none, s_);
+        dslash(lat_, gauge64_, k, 1, t64_, ax64_, nullptr, none, s_);
+        launch_residual(r64_, bp_, ax64_, rt, s_);
+    }
+    launch_convert(r64_, rl_, gate(), s_);
+    launch_restart_p(pl_, rl_, gate(), s_);
+}
+
+void Solve::enqueue_finish() {
+    const double k = p_.kappa;
+    const Gate none{nullptr, nullptr};
+    launch_accum_zero(x64_, xl_, st_, s_);
+    dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, none, s_);
+    RedArgs ra = red(RED_AUX);
+    launch_residual(ax64_, b64_, t64_, ra, s_);  // |b - D x|^2
+    RedArgs rb = red(RED_AUX2);
+    launch_norm(b64_, rb, s_);                  // |b|^2
+    launch_export(x64_, x_, s_);
+    final_slot_ = 0;
+    (void)hipMemcpyAsync(h_st_, st_, sizeof(RhsState) * p_.nrhs, hipMemcpyDeviceToHost, s_);
+    (void)hipEventRecord(final_ev_, s_);
+}
+
+int Solve::push_status() {
+    // reuse a slot only once its previous copy has been consumed
+    const int slot = next_slot_;
+    next_slot_ = (next_slot_ + 1) % kSlots;
+    RhsState *hs = h_st_ + (size_t)slot * p_.nrhs;
+    if (hipMemcpyAsync(hs, st_, sizeof(RhsState) * p_.nrhs, hipMemcpyDeviceToHost, s_) !=
+            hipSuccess ||
+        hipMemcpyAsync(h_batch_ + slot, batch_, sizeof(BatchState), hipMemcpyDeviceToHost, s_) !=
+            hipSuccess ||
+        hipEventRecord(events_[slot], s_) != hipSuccess)
+        return fail(WD_ERR_HIP, "status copy failed");
+    pending_.push_back(Pending{events_[slot], slot, epoch_});
+    return WD_OK;
+}
+
+int Solve::advance(bool block) {
+    for (;;) {
+        if (phase_ == 2) return 1;
+        if (phase_ == 1) {
+            hipError_t e = block ? hipEventSynchronize(final_ev_) : hipEventQuery(final_ev_);
+            if (e == hipErrorNotReady) return 0;
+            if (e != hipSuccess) return fail(WD_ERR_HIP, "solve failed on the device: %s",
+                                             hipGetErrorString(e));
+            result_ = WD_OK;
+            for (int r = 0; r < p_.nrhs; ++r) {
+                const RhsState &st = h_st_[r];
+                if (!st.converged) {
+                    result_ = st.failed ? st.failed : WD_ERR_NOCONV;
+                    break;
+                }
+            }
+            phase_ = 2;
+            return 1;
+        }
+        // keep two status reads in flight so the device never idles on the host
+        while (pending_.size() < 2) {
+            enqueue_inner(chunk_);
+            if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "kernel launch failed");
+            int rc = push_status();
+            if (rc) return rc;
+        }
+        Pending f = pending_.front();
+        hipError_t e = block ? hipEventSynchronize(f.ev) : hipEventQuery(f.ev);
+        if (e == hipErrorNotReady) return 0;
+        if (e != hipSuccess) return fail(WD_ERR_HIP, "solve failed on the device: %s",
+                                         hipGetErrorString(e));
+        pending_.pop_front();
+        if (f.epoch != epoch_) continue;  // taken before the last reliable update
+        const BatchState &bs = h_batch_[f.slot];
+        if (bs.n_active > 0) continue;
+        if (bs.n_trigger > 0) {
+            enqueue_reliable(false);
+            ++epoch_;
+            int rc = push_status();
+            if (rc) return rc;
+            continue;
+        }
+        // every rhs converged or failed: pending inner chunks are no-ops
+        enqueue_finish();
+        if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "kernel launch failed");
+        phase_ = 1;
+    }
+}
+
+void Solve::info(wd_solve_info *out) const {
+    for (int r = 0; r < p_.nrhs; ++r) {
+        const RhsState &st = h_st_[r];
+        wd_solve_info &o = out[r];
+        o.status = st.converged ? WD_OK : (st.failed ? st.failed : WD_ERR_NOCONV);
+        o.iters = st.iters;
+        o.reliable_updates = st.updates;
+        o.true_rel_resid = st.rr0 > 0 ? std::sqrt(st.rr_true / st.rr0) : 0.0;
+        o.rel_resid_D = st.aux2 > 0 ? std::sqrt(st.aux / st.aux2) : 0.0;
+        o.seconds = seconds;
+    }
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" int wd_cg_solve(wd_lattice *lat, const wd_solve_params *p, const double *b,
+                           double *x, wd_solve_info *info, void *stream) {
+    int rc = Solve::validate(lat, p);
+    if (rc) return rc;
+    if (!b || !x || !info) return fail(WD_ERR_ARG, "null argument");
+    if (b == x) return fail(WD_ERR_ARG, "b and x must not overlap");
+    const double t0 = now_seconds();
+    Solve s(lat, *p, b, x);
+    rc = s.setup((hipStream_t)stream);
+    if (rc) return rc;
+    rc = s.start();
+    if (rc) return rc;
+    for (;;) {
+        int a = s.advance(true);
+        if (a < 0) return a;
+        if (a == 1) break;
+    }
+    s.seconds = now_seconds() - t0;
+    s.info(info);
+    return s.result();
+}

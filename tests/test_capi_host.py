@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/wd.h declares, and rejects invalid arguments before
+any HIP call."""
+import ctypes
+import subprocess
+
+import pytest
+
+import paper_1810_04201_amd as wd
+
+
+def test_header_symbols_exported():
+    names = wd.header_functions()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", wd.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(wd.lib, n)
+
+
+def test_binding_covers_header():
+    assert set(wd.header_functions()) == set(wd._SIGS)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 4, 4), (4, 4, 0, 4), (4, 4, 4, 1), (-2, 4, 4, 4)])
+def test_bad_dims_rejected(dims):
+    d = (ctypes.c_int32 * 4)(*dims)
+    h = ctypes.c_void_p()
+    rc = wd.lib.wd_create_lattice(d, 1, ctypes.byref(h))
+    assert rc == wd.WD_ERR_ARG
+    assert "even" in wd.last_error()
+    assert not h.value
+
+
+def test_bad_flags_and_null():
+    d = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    h = ctypes.c_void_p()
+    assert wd.lib.wd_create_lattice(d, 0x10, ctypes.byref(h)) == wd.WD_ERR_ARG
+    assert wd.lib.wd_create_lattice(None, 1, ctypes.byref(h)) == wd.WD_ERR_ARG
+    assert wd.lib.wd_destroy_lattice(None) == wd.WD_ERR_ARG
+    assert wd.lib.wd_poll(None, 1, None) in (wd.WD_ERR_ARG, wd.WD_ERR_STATE)
+
+
+def test_lattice_lifecycle_host_only():
+    lat = wd.Lattice((4, 6, 8, 10))
+    assert lat.volume == 1920
+    v = ctypes.c_int64()
+    assert wd.lib.wd_lattice_volume(lat.handle, ctypes.byref(v)) == 0 and v.value == 1920
+    assert lat.gauge_bytes() == 0
+    lat.close()
+
+
+def test_solve_rejected_without_gauge_and_bad_params():
+    lat = wd.Lattice((4, 4, 4, 4))
+    infos = (wd.wd_solve_info * 1)()
+    p = wd.make_params(0.12, tol=1e-10)
+    dummy = ctypes.c_void_p(16)
+    assert wd.lib.wd_cg_solve(lat.handle, ctypes.byref(p), dummy, ctypes.c_void_p(32), infos,
+                              None) == wd.WD_ERR_NOGAUGE
+    for bad in (wd.make_params(0.12, tol=0.0), wd.make_params(0.12, nrhs=13),
+                wd.make_params(0.12, nrhs=0), wd.make_params(float("nan")),
+                wd.make_params(0.12, max_iter=0), wd.make_params(0.12, prec=2)):
+        if bad.prec_inner == 2:
+            bad.prec_inner = 7
+        assert wd.lib.wd_cg_solve(lat.handle, ctypes.byref(bad), dummy, ctypes.c_void_p(32),
+                                  infos, None) == wd.WD_ERR_ARG
+    lat.close()
+
+
+def test_apply_rejects_bad_args_before_gpu():
+    lat = wd.Lattice((4, 4, 4, 4))
+    a, b = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    assert wd.lib.wd_apply(lat.handle, 0.1, 9, 0, 1, a, b, None) == wd.WD_ERR_ARG
+    assert wd.lib.wd_apply(lat.handle, 0.1, 0, 0, 13, a, b, None) == wd.WD_ERR_ARG
+    assert wd.lib.wd_apply(lat.handle, 0.1, 0, 2, 1, a, b, None) == wd.WD_ERR_ARG
+    assert wd.lib.wd_apply(lat.handle, float("inf"), 0, 0, 1, a, b, None) == wd.WD_ERR_ARG
+    assert wd.lib.wd_apply(lat.handle, 0.1, 0, 0, 1, a, a, None) == wd.WD_ERR_ARG
+    # no gauge yet: refused before any device work
+    assert wd.lib.wd_apply(lat.handle, 0.1, 0, 0, 1, a, b, None) == wd.WD_ERR_NOGAUGE
+    lat.close()

@@ -1,0 +1,188 @@
+"""Parity of the HIP CG solve (wd_cg_solve) with the CPU oracle.
+
+FP64 CG: solution within 1e-9 of the oracle's CGNR (same tolerance) and
+iteration count within +-1; the true normal residual meets the tolerance.
+Mixed precision (FP32 / FP16 inner, FP64 reliable updates) and 12-rhs
+batches: FP64 true residual <= tol and each solution within the bound that
+the problem's condition number allows, against the oracle.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cg, dense, wilson
+from gpu_util import gauge, rel, vol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_1810_04201_amd as wd
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0"), wd
+
+
+def _solve(env, dims, U, b, kappa, tol=1e-10, prec="f64", nrhs=1, **kw):
+    torch, dev, wd = env
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    bd = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    xd = torch.zeros_like(bd)
+    rc, info = lat.solve(bd, xd, kappa, tol=tol, prec=prec, nrhs=nrhs, **kw)
+    torch.cuda.synchronize()
+    x = xd.cpu().numpy()
+    lat.close()
+    return rc, info, x
+
+
+def _oracle(dims, U, b, kappa, tol):
+    x, it, info = cg.cgnr(lambda v: wilson.apply_D(U, v, dims, kappa),
+                          lambda v: wilson.apply_Ddag(U, v, dims, kappa), b, tol=tol)
+    return x, it, info
+
+
+@pytest.mark.parametrize("dims,seed,kind,kappa,src", [
+    ((4, 4, 4, 4), 1, "haar", 0.12, "point"),      # the 4^4 configuration
+    ((4, 6, 8, 10), 5, "exp", 0.124, "gauss"),
+    ((8, 8, 8, 8), 6, "exp", 0.124, "gauss"),
+    ((2, 4, 2, 6), 7, "haar", 0.15, "gauss"),
+])
+def test_fp64_cg_matches_oracle(env, dims, seed, kind, kappa, src):
+    print(f"fp64 cg dims={dims}", flush=True)
+    U = gauge(dims, seed, kind)
+    b = synth.point_source(dims) if src == "point" else synth.gaussian_spinor(dims, seed + 100)
+    rc, info, x = _solve(env, dims, U, b, kappa, tol=1e-10)
+    _, dev, wd = env
+    assert rc == wd.WD_OK, info
+    xo, it, oinfo = _oracle(dims, U, b, kappa, 1e-10)
+    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+    assert abs(info[0]["iters"] - it) <= 1, (info[0]["iters"], it)
+    assert info[0]["true_rel_resid"] <= 1e-10
+    assert rel(x, xo) <= max(1e-9, 2e-10 * cond), (rel(x, xo), cond)
+    # the reported ||b - D x|| / ||b|| agrees with the oracle's own operator
+    r = b - wilson.apply_D(U, x, dims, kappa)
+    rD = np.linalg.norm(r) / np.linalg.norm(b)
+    assert abs(rD - info[0]["rel_resid_D"]) <= 1e-3 * rD + 1e-15
+
+
+def test_fp64_cg_vs_dense_lapack_2x4(env):
+    dims = (2, 2, 2, 2)
+    U = gauge(dims, 1, "haar")
+    b = synth.gaussian_spinor(dims, 2)
+    rc, info, x = _solve(env, dims, U, b, 0.12, tol=1e-13)
+    assert rc == 0
+    M = dense.dense_D(U, dims, 0.12)
+    want = dense.unflat(np.linalg.solve(M, dense.flat(b)))
+    assert rel(x, want) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("dims,seed,kappa", [((4, 4, 4, 4), 1, 0.12), ((8, 8, 8, 8), 6, 0.124),
+                                             ((4, 6, 8, 10), 5, 0.124)])
+def test_mixed_precision_matches_fp64(env, prec, dims, seed, kappa):
+    print(f"mixed {prec} dims={dims}", flush=True)
+    U = gauge(dims, seed, "haar" if dims == (4, 4, 4, 4) else "exp")
+    b = synth.gaussian_spinor(dims, seed + 200)
+    tol = 1e-10
+    rc, info, x = _solve(env, dims, U, b, kappa, tol=tol, prec=prec)
+    assert rc == 0, info
+    assert info[0]["true_rel_resid"] <= tol
+    assert info[0]["reliable_updates"] >= 2
+    xo, it, oinfo = _oracle(dims, U, b, kappa, 1e-12)
+    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+    assert rel(x, xo) <= max(1e-9, 2 * tol * cond), (rel(x, xo), cond)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_multi_rhs_12_point_sources(env, prec):
+    dims = (4, 6, 4, 8)
+    U = gauge(dims, 4)
+    B = synth.spin_colour_point_sources(dims)
+    rc, info, X = _solve(env, dims, U, B, 0.124, tol=1e-10, prec=prec, nrhs=12)
+    assert rc == 0, info
+    for k in range(12):
+        assert info[k]["status"] == 0
+        assert info[k]["true_rel_resid"] <= 1e-10
+        xo, it, oinfo = _oracle(dims, U, B[k], 0.124, 1e-12)
+        cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+        assert rel(X[k], xo) <= max(1e-9, 2e-10 * cond)
+        if prec == "f64":
+            assert abs(info[k]["iters"] - cg.cgnr(
+                lambda v: wilson.apply_D(U, v, dims, 0.124),
+                lambda v: wilson.apply_Ddag(U, v, dims, 0.124), B[k], tol=1e-10)[1]) <= 1
+
+
+def test_multi_rhs_column_equals_single(env):
+    dims = (4, 4, 4, 8)
+    U = gauge(dims, 9)
+    B = synth.gaussian_sources(dims, [1, 2, 3, 4, 5])
+    rc, info, X = _solve(env, dims, U, B, 0.124, tol=1e-11, prec="f32", nrhs=5)
+    assert rc == 0
+    for k in (0, 3):
+        rc1, info1, x1 = _solve(env, dims, U, B[k], 0.124, tol=1e-11, prec="f32")
+        assert rc1 == 0
+        assert rel(X[k], x1) < 1e-9
+
+
+def test_deterministic_bitwise(env):
+    dims = (4, 6, 8, 10)
+    U = gauge(dims, 12)
+    b = synth.gaussian_spinor(dims, 13)
+    _, _, x1 = _solve(env, dims, U, b, 0.124, prec="f16")
+    _, _, x2 = _solve(env, dims, U, b, 0.124, prec="f16")
+    assert np.array_equal(x1, x2)
+
+
+def test_zero_source_and_warm_start(env):
+    torch, dev, wd = env
+    dims = (4, 4, 4, 4)
+    U = gauge(dims, 1, "haar")
+    rc, info, x = _solve(env, dims, U, np.zeros((vol(dims), 4, 3, 2)), 0.12)
+    assert rc == 0 and info[0]["iters"] == 0 and not np.any(x)
+    b = synth.gaussian_spinor(dims, 3)
+    rc, info, x = _solve(env, dims, U, b, 0.12, tol=1e-12)
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    bd = torch.from_numpy(b).to(dev)
+    xd = torch.from_numpy(x).to(dev)
+    rc2, info2 = lat.solve(bd, xd, 0.12, tol=1e-10, x0_given=True)
+    assert rc2 == 0 and info2[0]["iters"] == 0
+    lat.close()
+
+
+def test_failure_paths(env):
+    torch, dev, wd = env
+    dims = (4, 4, 4, 4)
+    U = gauge(dims, 1, "haar")
+    b = synth.gaussian_spinor(dims, 3)
+    rc, info, x = _solve(env, dims, U, b, 0.12, max_iter=2)
+    assert rc == wd.WD_ERR_NOCONV and info[0]["status"] == wd.WD_ERR_NOCONV
+    assert info[0]["iters"] == 2 and np.all(np.isfinite(x))
+    bn = b.copy()
+    bn[5, 1, 1, 0] = np.nan
+    rc, info, x = _solve(env, dims, U, bn, 0.12)
+    assert rc == wd.WD_ERR_NUMERIC
+    # one bad column fails only itself
+    B = np.stack([b, bn, 2 * b])
+    rc, info, X = _solve(env, dims, U, B, 0.12, nrhs=3)
+    assert rc == wd.WD_ERR_NUMERIC
+    assert info[0]["status"] == 0 and info[2]["status"] == 0
+    assert info[1]["status"] == wd.WD_ERR_NUMERIC
+    assert rel(X[2], 2 * X[0]) < 1e-9
+
+
+def test_config2_16x32_true_residual_by_oracle(env):
+    """16^3 x 32, kappa 0.124, eps = 0.3 links seed 2, Gaussian source seed 102."""
+    dims = (16, 16, 16, 32)
+    print("fp64 cg 16^3x32", flush=True)
+    U = gauge(dims, 2)
+    b = synth.gaussian_spinor(dims, 102)
+    for prec in ("f64", "f32", "f16"):
+        rc, info, x = _solve(env, dims, U, b, 0.124, prec=prec)
+        assert rc == 0, (prec, info)
+        bp = wilson.apply_Ddag(U, b, dims, 0.124)
+        r = bp - wilson.apply_DdagD(U, x, dims, 0.124)
+        assert np.linalg.norm(r) / np.linalg.norm(bp) <= 1.0001e-10, prec
