@@ -22,7 +22,8 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwdirac.so")
+# WDIRAC_LIB may point at another build of the same library (tuning variants)
+LIB_PATH = os.environ.get("WDIRAC_LIB") or os.path.join(HERE, "libwdirac.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "wd.h")
 
 WD_OK = 0
@@ -111,6 +112,10 @@ def header_functions(path: str = HEADER):
 
 
 def _load():
+    # PyTorch ships its own libamdhip64.so.7 (same soname as the system one).
+    # Import it first so that the library binds to the runtime torch already
+    # uses: one HIP runtime per process, or neither sees the GPU.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "

@@ -10,6 +10,40 @@ namespace wd {
 
 static constexpr int kBS = 256;
 
+// ------------------------------------------------------------------ reduction phase 2
+
+// One block: fixed-order sum of nb partials per rhs, then the finaliser.
+// gated: skip when no rhs is iterating (the producing kernel returned early
+// and wrote no partials).
+constexpr int kFinalizeThreads = 256;
+
+__global__ void __launch_bounds__(kFinalizeThreads) k_finalize(RedArgs red, int nb, int gated) {
+    if (gated && red.batch->n_active == 0) return;
+    __shared__ double sm[kFinalizeThreads];
+    const int nrhs = red.ctl.nrhs;
+    const int tid = threadIdx.x;
+    int S = kFinalizeThreads;
+    while (S * nrhs > kFinalizeThreads) S >>= 1;
+    const int slot = tid / nrhs;
+    const int r = tid - slot * nrhs;
+    double acc = 0.0;
+    if (slot < S)
+        for (int b = slot; b < nb; b += S) acc += red.partials[(size_t)b * nrhs + r];
+    sm[tid] = acc;
+    __syncthreads();
+    for (int stride = S >> 1; stride > 0; stride >>= 1) {
+        if (tid < stride * nrhs) sm[tid] += sm[tid + stride * nrhs];
+        __syncthreads();
+    }
+    if (tid < nrhs && red.mode != RED_NONE) finalize_rhs(red, tid, sm[tid]);
+    __syncthreads();
+    if (tid == 0 && red.mode != RED_NONE) recount_batch(red);
+}
+
+void launch_finalize(const RedArgs &red, int nb, bool gated, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, s, red, nb, gated ? 1 : 0);
+}
+
 // ------------------------------------------------------------------ gauge
 
 // canonical [s][mu][a][b][re,im] -> F64-18 planes (mu, k = 3a+b) over sites
@@ -232,7 +266,7 @@ __global__ void k_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, Red
         Spinor<PX>::store(x, e, xv);
         Spinor<PX>::store(r, e, rv);
     }
-    reduce_finalize(nrm, red, nrhs);
+    reduce_block(nrm, red.partials, nrhs);
 }
 
 // p = r + beta p (RESTART: at the first reliable update p = r)
@@ -263,22 +297,17 @@ __global__ void k_update_p(FieldRef p, FieldRef r, Gate gate) {
     Spinor<PPP>::store(p, e, o);
 }
 
-static void check_pair(int px, int pp) {
-    (void)px;
-    (void)pp;
-}
-
 void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const RedArgs &red,
                       Gate gate, hipStream_t s) {
     const int bs = block_for_nrhs(x.nrhs);
     const int nb = blocks_for(x.n, bs);
-    check_pair(x.prec, p.prec);
     if (x.prec == WD_F64)
         hipLaunchKernelGGL((k_update_xr<WD_F64, WD_F64>), dim3(nb), dim3(bs), 0, s, x, r, p, Ap, red, gate);
     else if (p.prec == WD_F32)
         hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F32>), dim3(nb), dim3(bs), 0, s, x, r, p, Ap, red, gate);
     else
         hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F16>), dim3(nb), dim3(bs), 0, s, x, r, p, Ap, red, gate);
+    launch_finalize(red, nb, true, s);
 }
 
 template <bool RESTART>
@@ -320,7 +349,7 @@ __global__ void k_residual(FieldRef r, FieldRef b, FieldRef Ax, RedArgs red) {
         for (int k = 0; k < 12; ++k) nrm += bv[k].re * bv[k].re + bv[k].im * bv[k].im;
         Spinor<WD_F64>::store(r, e, bv);
     }
-    reduce_finalize(nrm, red, nrhs);
+    reduce_block(nrm, red.partials, nrhs);
 }
 
 template <int PREC>
@@ -333,21 +362,24 @@ __global__ void k_norm(FieldRef f, RedArgs red) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) nrm += v[k].re * v[k].re + v[k].im * v[k].im;
     }
-    reduce_finalize(nrm, red, f.nrhs);
+    reduce_block(nrm, red.partials, f.nrhs);
 }
 
 void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, hipStream_t s) {
     const int bs = block_for_nrhs(r.nrhs);
-    hipLaunchKernelGGL(k_residual, dim3(blocks_for(r.n, bs)), dim3(bs), 0, s, r, b, Ax, red);
+    const int nb = blocks_for(r.n, bs);
+    hipLaunchKernelGGL(k_residual, dim3(nb), dim3(bs), 0, s, r, b, Ax, red);
+    launch_finalize(red, nb, false, s);
 }
 
 void launch_norm(FieldRef f, const RedArgs &red, hipStream_t s) {
     const int bs = block_for_nrhs(f.nrhs);
-    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_norm<PP>, dim3(blocks_for(f.n, bs)), dim3(bs),
-                                                0, s, f, red));
+    const int nb = blocks_for(f.n, bs);
+    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_norm<PP>, dim3(nb), dim3(bs), 0, s, f, red));
+    launch_finalize(red, nb, false, s);
 }
 
-__global__ void k_init_state(RhsState *st, BatchState *batch, unsigned *ticket, int nrhs) {
+__global__ void k_init_state(RhsState *st, BatchState *batch, int nrhs) {
     const int r = threadIdx.x;
     if (r < nrhs) {
         RhsState z{};
@@ -358,13 +390,11 @@ __global__ void k_init_state(RhsState *st, BatchState *batch, unsigned *ticket, 
         batch->n_trigger = 0;
         batch->n_done = 0;
         batch->pad = 0;
-        *ticket = 0u;
     }
 }
 
-void launch_init_state(RhsState *st, BatchState *batch, unsigned *ticket, int nrhs,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, batch, ticket, nrhs);
+void launch_init_state(RhsState *st, BatchState *batch, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, batch, nrhs);
 }
 
 }  // namespace wd

@@ -186,11 +186,13 @@ struct Link<WD_F16> {
 
 // ------------------------------------------------------------------ reduction
 //
-// Deterministic: a fixed butterfly inside each wave (nrhs == 1) or a fixed
-// LDS tree over site slots (nrhs > 1), one partial per block and rhs, and
-// the last block to arrive (atomic ticket) sums the partials in a fixed
-// order and runs the finaliser.  Results are bitwise reproducible for a
-// given launch shape, independent of block scheduling.
+// Deterministic and split in two launches: every block of the producing
+// kernel reduces its contribution (a fixed butterfly inside each wave for
+// nrhs == 1, a fixed LDS tree over site slots for nrhs > 1) and writes one
+// partial per rhs; a one-block finalize kernel then sums the partials in a
+// fixed order and updates the solver state.  The kernel boundary orders the
+// two phases, so no device-scope fence (an L2 write-back on this chip) is
+// issued per block.  Results are bitwise reproducible for a launch shape.
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
@@ -292,16 +294,14 @@ __device__ inline void recount_batch(const RedArgs &red) {
     red.batch->n_done = nd;
 }
 
-// v: this thread's contribution (0 for idle threads).  Must be reached by
-// every thread of every block of the launch.  blockDim.x = S * nrhs with S a
-// power of two and the block's first entry a multiple of nrhs, so thread t
-// belongs to rhs t % nrhs.
-__device__ inline void reduce_finalize(double v, const RedArgs &red, int nrhs) {
-    __shared__ double sm[1024];
-    __shared__ int am_last;
+// Phase 1.  v: this thread's contribution (0 for idle threads).  Must be
+// reached by every thread of the block.  blockDim.x = S * nrhs with S a power
+// of two and the block's first entry a multiple of nrhs, so thread t belongs
+// to rhs t % nrhs.  Writes partials[blockIdx.x * nrhs + rhs].
+__device__ inline void reduce_block(double v, double *partials, int nrhs) {
+    __shared__ double sm[256];
     const int tid = threadIdx.x;
     const int bd = blockDim.x;
-    const int S = bd / nrhs;
     if (nrhs == 1) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -310,45 +310,20 @@ __device__ inline void reduce_finalize(double v, const RedArgs &red, int nrhs) {
         if (tid == 0) {
             double s = 0.0;
             for (int w = 0; w < (bd >> 6); ++w) s += sm[w];
-            red.partials[blockIdx.x] = s;
+            partials[blockIdx.x] = s;
         }
     } else {
+        const int S = bd / nrhs;
         sm[tid] = v;
         __syncthreads();
         for (int stride = S >> 1; stride > 0; stride >>= 1) {
             if (tid < stride * nrhs) sm[tid] += sm[tid + stride * nrhs];
             __syncthreads();
         }
-        if (tid < nrhs) red.partials[(size_t)blockIdx.x * nrhs + tid] = sm[tid];
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        unsigned prev = atomicAdd(red.ticket, 1u);
-        am_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
-    const int nb = gridDim.x;
-    const int slot = tid / nrhs;
-    const int r = tid - slot * nrhs;
-    double acc = 0.0;
-    const volatile double *part = red.partials;
-    for (int b = slot; b < nb; b += S) acc += part[(size_t)b * nrhs + r];
-    sm[tid] = acc;
-    __syncthreads();
-    for (int stride = S >> 1; stride > 0; stride >>= 1) {
-        if (tid < stride * nrhs) sm[tid] += sm[tid + stride * nrhs];
-        __syncthreads();
-    }
-    if (tid < nrhs && red.mode != RED_NONE) finalize_rhs(red, tid, sm[tid]);
-    __syncthreads();
-    if (tid == 0) {
-        if (red.mode != RED_NONE) recount_batch(red);
-        *red.ticket = 0u;
-        __threadfence();
+        if (tid < nrhs) partials[(size_t)blockIdx.x * nrhs + tid] = sm[tid];
     }
 }
+
+// Phase 2 is k_finalize (blas.hip), launched by launch_finalize.
 
 }  // namespace wd

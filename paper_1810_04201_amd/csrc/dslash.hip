@@ -20,6 +20,9 @@
 // coalesced 16-byte loads from the structure-of-arrays planes.
 #include "device.hpp"
 
+#ifndef WD_XCD_REMAP
+#define WD_XCD_REMAP 1
+#endif
 #ifndef WD_GROUP_F64
 #define WD_GROUP_F64 1
 #endif
@@ -122,6 +125,20 @@ __device__ __forceinline__ void hop(const void *gauge, int V, const FieldRef &in
     accumulate<MU, S>(w0, w1, acc);
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// With WD_XCD_REMAP each XCD instead walks one contiguous run of logical
+// blocks, so that neighbours within a few thousand sites share an L2.
+__device__ __forceinline__ int logical_block() {
+#if WD_XCD_REMAP
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, i = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + i;
+#else
+    return blockIdx.x;
+#endif
+}
+
 template <int PREC, bool DAG, bool RED, int GROUP>
 __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__ gauge, FieldRef in,
                                                 FieldRef out, double kappa_d, RedArgs red,
@@ -129,7 +146,7 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
     using R = typename Spinor<PREC>::R;
     if (gate.batch && gate.batch->n_active == 0) return;  // grid-uniform
     const int nrhs = in.nrhs;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = logical_block() * blockDim.x + threadIdx.x;
     bool live = e < in.n;
     const int site = e / nrhs;
     const int rhs = e - site * nrhs;
@@ -195,7 +212,7 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
         }
         Spinor<PREC>::store(out, e, c);
     }
-    if (RED) reduce_finalize(nrm, red, nrhs);
+    if (RED) reduce_block(nrm, red.partials, nrhs);
 }
 
 // hops per scheduling group (see k_dslash)
@@ -226,6 +243,7 @@ static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagg
             hipLaunchKernelGGL((k_dslash<PREC, false, false, HopGroup<PREC>::value>), dim3(nb), dim3(bs), 0, s, g, gauge,
                                in, out, kappa, r, gate);
     }
+    if (red) launch_finalize(r, nb, gate.batch != nullptr, s);
 }
 
 void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,

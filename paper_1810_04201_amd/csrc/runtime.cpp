@@ -60,9 +60,10 @@ void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err) {
     }
     if (lat->gauge[prec]) return lat->gauge[prec];
     void *p = nullptr;
-    if (hipMalloc(&p, gauge_bytes(prec, lat->g.V)) != hipSuccess) {
-        *err = fail(WD_ERR_NOMEM, "hipMalloc of the %s gauge form failed",
-                    prec == WD_F32 ? "F32-12" : "F16-12");
+    hipError_t he = hipMalloc(&p, gauge_bytes(prec, lat->g.V));
+    if (he != hipSuccess) {
+        *err = fail(WD_ERR_NOMEM, "hipMalloc of the %s gauge form failed: %s",
+                    prec == WD_F32 ? "F32-12" : "F16-12", hipGetErrorString(he));
         return nullptr;
     }
     launch_gauge_lo(lat->gauge[WD_F64], p, prec, lat->g.V, s);
@@ -205,8 +206,10 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
         return fail(WD_ERR_STATE, "gauge cannot change while requests are in flight");
     if (!lat->gauge[WD_F64]) {
         void *p = nullptr;
-        if (hipMalloc(&p, gauge_bytes(WD_F64, lat->g.V)) != hipSuccess)
-            return fail(WD_ERR_NOMEM, "hipMalloc of the F64 gauge form failed");
+        hipError_t he = hipMalloc(&p, gauge_bytes(WD_F64, lat->g.V));
+        if (he != hipSuccess)
+            return fail(WD_ERR_NOMEM, "hipMalloc of the F64 gauge form failed: %s",
+                        hipGetErrorString(he));
         lat->gauge[WD_F64] = p;
     }
     launch_pack_gauge_f64(U, lat->gauge[WD_F64], lat->g.V, s);
@@ -225,9 +228,10 @@ int wd_field_create(wd_lattice *lat, int prec, int nrhs, wd_field **out) {
     wd_field *f = new (std::nothrow) wd_field();
     if (!f) return fail(WD_ERR_NOMEM, "host allocation failed");
     size_t bytes = spinor_bytes(prec, (int64_t)lat->g.V * nrhs) + 256;
-    if (hipMalloc(&f->mem, bytes) != hipSuccess) {
+    hipError_t he = hipMalloc(&f->mem, bytes);
+    if (he != hipSuccess) {
         delete f;
-        return fail(WD_ERR_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+        return fail(WD_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(he));
     }
     char *cur = (char *)f->mem;
     f->ref = carve(cur, prec, nrhs, lat->g.V);
@@ -292,8 +296,10 @@ int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, cons
     const int V = lat->g.V;
     size_t one = spinor_bytes(prec, (int64_t)V * nrhs) + 256;
     void *mem = nullptr;
-    if (hipMallocAsync(&mem, 2 * one, s) != hipSuccess)
-        return fail(WD_ERR_NOMEM, "workspace allocation of %zu bytes failed", 2 * one);
+    hipError_t he = hipMallocAsync(&mem, 2 * one, s);
+    if (he != hipSuccess)
+        return fail(WD_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s", 2 * one,
+                    hipGetErrorString(he));
     char *cur = (char *)mem;
     FieldRef a = carve(cur, prec, nrhs, V);
     cur = (char *)mem + one;

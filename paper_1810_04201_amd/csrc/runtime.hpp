@@ -97,7 +97,6 @@ class Solve {
     FieldRef xl_{}, rl_{}, pl_{}, tl_{}, apl_{};
     RhsState *st_ = nullptr;
     BatchState *batch_ = nullptr;
-    unsigned *ticket_ = nullptr;
     double *partials_ = nullptr;
     SolveCtl ctl_{};
     // pinned status ring

@@ -61,7 +61,7 @@ size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
     b += 2 * field_bytes(lo_xr, n) + 3 * field_bytes(lo, n);
     const int bs = block_for_nrhs(p.nrhs);
     b += align256((size_t)(blocks_for(n, bs) + 1) * p.nrhs * sizeof(double));
-    b += align256(sizeof(RhsState) * 12) + 2 * 256;
+    b += align256(sizeof(RhsState) * 12) + 256;
     return b;
 }
 
@@ -80,9 +80,11 @@ int Solve::setup(hipStream_t stream) {
         gauge_lo_ = gauge64_;
     }
     bytes_ = footprint(lat_, p_);
-    if (hipMalloc(&mem_, bytes_) != hipSuccess) {
+    hipError_t he = hipMalloc(&mem_, bytes_);
+    if (he != hipSuccess) {
         mem_ = nullptr;
-        return fail(WD_ERR_NOMEM, "hipMalloc of %zu bytes of solver workspace failed", bytes_);
+        return fail(WD_ERR_NOMEM, "hipMalloc of %zu bytes of solver workspace failed: %s", bytes_,
+                    hipGetErrorString(he));
     }
     char *base = (char *)mem_;
     char *cur = base;
@@ -110,8 +112,6 @@ int Solve::setup(hipStream_t stream) {
     st_ = (RhsState *)cur;
     cur += align256(sizeof(RhsState) * 12);
     batch_ = (BatchState *)cur;
-    cur += 256;
-    ticket_ = (unsigned *)cur;
     cur += 256;
     if ((size_t)(cur - base) > bytes_) return fail(WD_ERR_STATE, "workspace layout overflow");
 
@@ -141,7 +141,6 @@ int Solve::setup(hipStream_t stream) {
 RedArgs Solve::red(int mode) const {
     RedArgs r{};
     r.partials = partials_;
-    r.ticket = ticket_;
     r.st = st_;
     r.batch = batch_;
     r.ctl = ctl_;
@@ -152,7 +151,7 @@ RedArgs Solve::red(int mode) const {
 int Solve::start() {
     const double k = p_.kappa;
     const Gate none{nullptr, nullptr};
-    launch_init_state(st_, batch_, ticket_, p_.nrhs, s_);
+    launch_init_state(st_, batch_, p_.nrhs, s_);
     launch_import(b_, b64_, s_);
     RedArgs rb = red(RED_B0);
     dslash(lat_, gauge64_, k, 1, b64_, bp_, &rb, none, s_);  // b' = D^dag b, |b'|^2

@@ -122,8 +122,7 @@ enum RedMode {
 };
 
 struct RedArgs {
-    double *partials;    // >= nblocks * nrhs doubles
-    unsigned *ticket;    // one counter, zero between launches
+    double *partials;    // >= nblocks * nrhs doubles (one per block and rhs)
     RhsState *st;        // nrhs entries
     BatchState *batch;
     SolveCtl ctl;
@@ -171,9 +170,11 @@ void launch_update_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s);
 void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, hipStream_t s);
 // reduce |f|^2 (any precision) with red.mode
 void launch_norm(FieldRef f, const RedArgs &red, hipStream_t s);
-// zero the states, the batch counters and the ticket
-void launch_init_state(RhsState *st, BatchState *batch, unsigned *ticket, int nrhs,
-                       hipStream_t s);
+// phase 2 of a reduction: one block sums the nb per-block partials in a fixed
+// order and runs the finaliser (gated: skip when no rhs is iterating)
+void launch_finalize(const RedArgs &red, int nb, bool gated, hipStream_t s);
+// zero the states and the batch counters
+void launch_init_state(RhsState *st, BatchState *batch, int nrhs, hipStream_t s);
 // after a reliable update, for the rhs it restarted (active): p = r at the
 // first update, p = r + beta p afterwards
 void launch_restart_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s);
