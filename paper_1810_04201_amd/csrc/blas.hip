@@ -46,65 +46,48 @@ void launch_finalize(const RedArgs &red, int nb, bool gated, hipStream_t s) {
 
 // ------------------------------------------------------------------ gauge
 
-// canonical [s][mu][a][b][re,im] -> F64-18 planes (mu, k = 3a+b) over sites
-__global__ void k_pack_gauge_f64(const double2 *__restrict__ canon, double2 *__restrict__ g,
-                                 int V) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
+// canonical [s][mu][a][b][re,im] (lexicographic s) -> F64-18 tiles in brick order
+__global__ void k_pack_gauge_f64(const double2 *__restrict__ canon, void *__restrict__ g, Geom geo) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= geo.V) return;
+    int x, y, z, t;
+    coords_of(geo, i, x, y, z, t);
+    const double2 *src = canon + (size_t)lex_of(geo, x, y, z, t) * 36;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu)
+    for (int mu = 0; mu < 4; ++mu) {
+        cx<double> u[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-            g[(size_t)(mu * 9 + k) * V + s] = canon[(size_t)s * 36 + mu * 9 + k];
-}
-
-// F64-18 planes -> 12-real forms (rows 0 and 1), rounded to nearest even
-__global__ void k_gauge_f32(const double2 *__restrict__ g, float4 *__restrict__ o, int V) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double2 a = g[(size_t)(mu * 9 + 2 * j) * V + s];
-            double2 b = g[(size_t)(mu * 9 + 2 * j + 1) * V + s];
-            o[(size_t)(mu * 3 + j) * V + s] = make_float4((float)a.x, (float)a.y, (float)b.x,
-                                                          (float)b.y);
+        for (int k = 0; k < 9; ++k) {
+            double2 d = src[mu * 9 + k];
+            u[k] = {d.x, d.y};
         }
+        Link<WD_F64>::store(g, mu, i, u);
+    }
 }
 
-__global__ void k_gauge_f16(const double2 *__restrict__ g, h4_t *__restrict__ o, int V) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
+// F64-18 -> 12-real forms (rows 0 and 1), rounded to nearest even
+template <int PREC>
+__global__ void k_gauge_lo(const void *__restrict__ g, void *__restrict__ o, int V) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double2 a = g[(size_t)(mu * 9 + 2 * j) * V + s];
-            double2 b = g[(size_t)(mu * 9 + 2 * j + 1) * V + s];
-            h4_t q;
-            // double -> float -> half: the float step is exact to 24 bits, the
-            // final rounding to 11 bits dominates
-            q[0] = (_Float16)(float)a.x;
-            q[1] = (_Float16)(float)a.y;
-            q[2] = (_Float16)(float)b.x;
-            q[3] = (_Float16)(float)b.y;
-            o[(size_t)(mu * 3 + j) * V + s] = q;
-        }
+    for (int mu = 0; mu < 4; ++mu) {
+        cx<double> u[9];
+        Link<WD_F64>::load(g, mu, i, u);
+        Link<PREC>::store(o, mu, i, u);
+    }
 }
 
-void launch_pack_gauge_f64(const double *canon, void *g64, int V, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_gauge_f64, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s,
-                       (const double2 *)canon, (double2 *)g64, V);
+void launch_pack_gauge_f64(const double *canon, void *g64, const Geom &geo, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_gauge_f64, dim3(blocks_for(geo.V, kBS)), dim3(kBS), 0, s,
+                       (const double2 *)canon, g64, geo);
 }
 
 void launch_gauge_lo(const void *g64, void *glo, int prec, int V, hipStream_t s) {
     if (prec == WD_F32)
-        hipLaunchKernelGGL(k_gauge_f32, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s,
-                           (const double2 *)g64, (float4 *)glo, V);
+        hipLaunchKernelGGL(k_gauge_lo<WD_F32>, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s, g64, glo, V);
     else
-        hipLaunchKernelGGL(k_gauge_f16, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s,
-                           (const double2 *)g64, (h4_t *)glo, V);
+        hipLaunchKernelGGL(k_gauge_lo<WD_F16>, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s, g64, glo, V);
 }
 
 // ------------------------------------------------------------------ spinors
@@ -126,13 +109,15 @@ __device__ __forceinline__ void store_from_double(const FieldRef &f, int i, cons
     Spinor<PREC>::store(f, i, t);
 }
 
-// canonical [rhs][s][12][re,im] -> field entry s*nrhs + rhs
+// canonical [rhs][s][12][re,im] (lexicographic s) -> field entry i*nrhs + rhs
 template <int PREC>
-__global__ void k_import(const double2 *__restrict__ canon, FieldRef f, int V) {
+__global__ void k_import(const double2 *__restrict__ canon, FieldRef f, Geom geo) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= f.n) return;
-    const int s = e / f.nrhs, r = e - s * f.nrhs;
-    const double2 *src = canon + ((size_t)r * V + s) * 12;
+    const int i = e / f.nrhs, r = e - i * f.nrhs;
+    int x, y, z, t;
+    coords_of(geo, i, x, y, z, t);
+    const double2 *src = canon + ((size_t)r * geo.V + lex_of(geo, x, y, z, t)) * 12;
     cx<double> v[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -143,13 +128,15 @@ __global__ void k_import(const double2 *__restrict__ canon, FieldRef f, int V) {
 }
 
 template <int PREC>
-__global__ void k_export(FieldRef f, double2 *__restrict__ canon, int V) {
+__global__ void k_export(FieldRef f, double2 *__restrict__ canon, Geom geo) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= f.n) return;
-    const int s = e / f.nrhs, r = e - s * f.nrhs;
+    const int i = e / f.nrhs, r = e - i * f.nrhs;
+    int x, y, z, t;
+    coords_of(geo, i, x, y, z, t);
     cx<double> v[12];
     load_as_double<PREC>(f, e, v);
-    double2 *dst = canon + ((size_t)r * V + s) * 12;
+    double2 *dst = canon + ((size_t)r * geo.V + lex_of(geo, x, y, z, t)) * 12;
 #pragma unroll
     for (int k = 0; k < 12; ++k) dst[k] = make_double2(v[k].re, v[k].im);
 }
@@ -200,16 +187,14 @@ __global__ void k_accum_zero(FieldRef x, FieldRef xl, const RhsState *st) {
         default: { constexpr int PP = WD_F16; __VA_ARGS__; } break;     \
     }
 
-void launch_import(const double *canon, FieldRef f, hipStream_t s) {
-    const int V = f.n / f.nrhs;
+void launch_import(const double *canon, FieldRef f, const Geom &geo, hipStream_t s) {
     WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_import<PP>, dim3(blocks_for(f.n, kBS)),
-                                                dim3(kBS), 0, s, (const double2 *)canon, f, V));
+                                                dim3(kBS), 0, s, (const double2 *)canon, f, geo));
 }
 
-void launch_export(FieldRef f, double *canon, hipStream_t s) {
-    const int V = f.n / f.nrhs;
+void launch_export(FieldRef f, double *canon, const Geom &geo, hipStream_t s) {
     WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_export<PP>, dim3(blocks_for(f.n, kBS)),
-                                                dim3(kBS), 0, s, f, (double2 *)canon, V));
+                                                dim3(kBS), 0, s, f, (double2 *)canon, geo));
 }
 
 template <int SRC>

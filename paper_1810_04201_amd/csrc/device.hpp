@@ -47,6 +47,14 @@ typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 
+// ------------------------------------------------------------------ tiles
+
+// address of the 16-byte element of plane k for entry i in a field whose
+// tiles are `tile_bytes` long
+__device__ __forceinline__ const char *tile_elem(const void *base, size_t tile_bytes, int i, int k) {
+    return (const char *)base + (size_t)(i >> 6) * tile_bytes + k * 1024 + (i & 63) * 16;
+}
+
 // ------------------------------------------------------------------ spinors
 
 template <int PREC>
@@ -55,38 +63,37 @@ struct Spinor;
 template <>
 struct Spinor<WD_F64> {
     using R = double;
+    static constexpr size_t kTileBytes = 12 * 1024;
     static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
-        const double2 *p = (const double2 *)f.data;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            double2 d = p[(size_t)k * f.n + i];
+            double2 d = *(const double2 *)tile_elem(f.data, kTileBytes, i, k);
             v[k] = {d.x, d.y};
         }
     }
     static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
-        double2 *p = (double2 *)f.data;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) p[(size_t)k * f.n + i] = make_double2(v[k].re, v[k].im);
+        for (int k = 0; k < 12; ++k)
+            *(double2 *)tile_elem(f.data, kTileBytes, i, k) = make_double2(v[k].re, v[k].im);
     }
 };
 
 template <>
 struct Spinor<WD_F32> {
     using R = float;
+    static constexpr size_t kTileBytes = 6 * 1024;
     static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
-        const float4 *p = (const float4 *)f.data;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            float4 q = p[(size_t)j * f.n + i];
+            float4 q = *(const float4 *)tile_elem(f.data, kTileBytes, i, j);
             v[2 * j] = {q.x, q.y};
             v[2 * j + 1] = {q.z, q.w};
         }
     }
     static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
-        float4 *p = (float4 *)f.data;
 #pragma unroll
         for (int j = 0; j < 6; ++j)
-            p[(size_t)j * f.n + i] =
+            *(float4 *)tile_elem(f.data, kTileBytes, i, j) =
                 make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
     }
 };
@@ -94,12 +101,16 @@ struct Spinor<WD_F32> {
 template <>
 struct Spinor<WD_F16> {
     using R = float;
+    static constexpr size_t kTileBytes = 3 * 1024 + 256;
+    static __device__ __forceinline__ const float *scale_ptr(const FieldRef &f, int i) {
+        return (const float *)((const char *)f.data + (size_t)(i >> 6) * kTileBytes + 3 * 1024 +
+                               (i & 63) * 4);
+    }
     static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
-        const h8_t *p = (const h8_t *)f.data;
-        const float s = f.scale[i];
+        const float s = *scale_ptr(f, i);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            h8_t q = p[(size_t)j * f.n + i];
+            h8_t q = *(const h8_t *)tile_elem(f.data, kTileBytes, i, j);
 #pragma unroll
             for (int m = 0; m < 4; ++m)
                 v[4 * j + m] = {s * (float)q[2 * m], s * (float)q[2 * m + 1]};
@@ -110,7 +121,6 @@ struct Spinor<WD_F16> {
 #pragma unroll
         for (int k = 0; k < 12; ++k) mx = fmaxf(mx, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
         const float inv = mx > 0.f ? 1.0f / mx : 0.f;
-        h8_t *p = (h8_t *)f.data;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             h8_t q;
@@ -119,9 +129,9 @@ struct Spinor<WD_F16> {
                 q[2 * m] = (_Float16)(v[4 * j + m].re * inv);
                 q[2 * m + 1] = (_Float16)(v[4 * j + m].im * inv);
             }
-            p[(size_t)j * f.n + i] = q;
+            *(h8_t *)tile_elem(f.data, kTileBytes, i, j) = q;
         }
-        f.scale[i] = mx;
+        *(float *)scale_ptr(f, i) = mx;
     }
 };
 
@@ -144,43 +154,71 @@ struct Link;
 template <>
 struct Link<WD_F64> {
     using R = double;
-    static __device__ __forceinline__ void load(const void *g, int V, int mu, int s, cx<R> u[9]) {
-        const double2 *p = (const double2 *)g + (size_t)mu * 9 * V;
+    static constexpr size_t kTileBytes = 36 * 1024;
+    static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            double2 d = p[(size_t)k * V + s];
+            double2 d = *(const double2 *)tile_elem(g, kTileBytes, s, mu * 9 + k);
             u[k] = {d.x, d.y};
         }
+    }
+    static __device__ __forceinline__ void store(void *g, int mu, int s, const cx<R> u[9]) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            *(double2 *)tile_elem(g, kTileBytes, s, mu * 9 + k) = make_double2(u[k].re, u[k].im);
     }
 };
 
 template <>
 struct Link<WD_F32> {
     using R = float;
-    static __device__ __forceinline__ void load(const void *g, int V, int mu, int s, cx<R> u[9]) {
-        const float4 *p = (const float4 *)g + (size_t)mu * 3 * V;
+    static constexpr size_t kTileBytes = 12 * 1024;
+    static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            float4 q = p[(size_t)j * V + s];
+            float4 q = *(const float4 *)tile_elem(g, kTileBytes, s, mu * 3 + j);
             u[2 * j] = {q.x, q.y};
             u[2 * j + 1] = {q.z, q.w};
         }
         reconstruct_row2(u);
+    }
+    static __device__ __forceinline__ void store(void *g, int mu, int s, const cx<double> u[9]) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            *(float4 *)tile_elem(g, kTileBytes, s, mu * 3 + j) =
+                make_float4((float)u[2 * j].re, (float)u[2 * j].im, (float)u[2 * j + 1].re,
+                            (float)u[2 * j + 1].im);
     }
 };
 
 template <>
 struct Link<WD_F16> {
     using R = float;
-    static __device__ __forceinline__ void load(const void *g, int V, int mu, int s, cx<R> u[9]) {
-        const h4_t *p = (const h4_t *)g + (size_t)mu * 3 * V;
+    static constexpr size_t kTileBytes = 12 * 512;
+    static __device__ __forceinline__ const char *elem(const void *g, int mu, int s, int j) {
+        return (const char *)g + (size_t)(s >> 6) * kTileBytes + (mu * 3 + j) * 512 + (s & 63) * 8;
+    }
+    static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            h4_t q = p[(size_t)j * V + s];
+            h4_t q = *(const h4_t *)elem(g, mu, s, j);
             u[2 * j] = {(float)q[0], (float)q[1]};
             u[2 * j + 1] = {(float)q[2], (float)q[3]};
         }
         reconstruct_row2(u);
+    }
+    static __device__ __forceinline__ void store(void *g, int mu, int s, const cx<double> u[9]) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            // double -> float -> half: the float step keeps 24 bits, the final
+            // rounding to 11 bits dominates
+            h4_t q;
+            q[0] = (_Float16)(float)u[2 * j].re;
+            q[1] = (_Float16)(float)u[2 * j].im;
+            q[2] = (_Float16)(float)u[2 * j + 1].re;
+            q[3] = (_Float16)(float)u[2 * j + 1].im;
+            *(h4_t *)elem(g, mu, s, j) = q;
+        }
     }
 };
 

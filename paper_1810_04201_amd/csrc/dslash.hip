@@ -18,6 +18,8 @@
 // Bandwidth bound: 1320 flop per site against 960 bytes (FP64, 18-real
 // links), so there is no matrix-core work here; the kernel is written for
 // coalesced 16-byte loads from the structure-of-arrays planes.
+#include <cstdlib>
+
 #include "device.hpp"
 
 #ifndef WD_XCD_REMAP
@@ -99,7 +101,7 @@ __device__ __forceinline__ void su3_mul(const cx<R> u[9], const cx<R> h[3], cx<R
 
 // one hop: project the neighbour spinor, multiply by the link, rebuild, add
 template <int MU, int S, bool BWD, int PREC>
-__device__ __forceinline__ void hop(const void *gauge, int V, const FieldRef &in, int nbr_entry,
+__device__ __forceinline__ void hop(const void *gauge, const FieldRef &in, int nbr_entry,
                                     int link_site, bool negate,
                                     cx<typename Spinor<PREC>::R> acc[12]) {
     using R = typename Spinor<PREC>::R;
@@ -118,7 +120,7 @@ __device__ __forceinline__ void hop(const void *gauge, int V, const FieldRef &in
         }
     }
     cx<R> u[9];
-    Link<PREC>::load(gauge, V, MU, link_site, u);
+    Link<PREC>::load(gauge, MU, link_site, u);
     cx<R> w0[3], w1[3];
     su3_mul<BWD>(u, h0, w0);
     su3_mul<BWD>(u, h1, w1);
@@ -139,6 +141,28 @@ __device__ __forceinline__ int logical_block() {
 #endif
 }
 
+// one hop with the link already in registers
+template <int MU, int S, bool BWD, int PREC>
+__device__ __forceinline__ void hop_u(const cx<typename Spinor<PREC>::R> u[9], const FieldRef &in,
+                                      int nbr_entry, bool negate,
+                                      cx<typename Spinor<PREC>::R> acc[12]) {
+    using R = typename Spinor<PREC>::R;
+    cx<R> p[12];
+    Spinor<PREC>::load(in, nbr_entry, p);
+    cx<R> h0[3], h1[3];
+    project<MU, S>(p, h0, h1);
+    const R sg = negate ? R(-1) : R(1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        h0[c] = scale(sg, h0[c]);
+        h1[c] = scale(sg, h1[c]);
+    }
+    cx<R> w0[3], w1[3];
+    su3_mul<BWD>(u, h0, w0);
+    su3_mul<BWD>(u, h1, w1);
+    accumulate<MU, S>(w0, w1, acc);
+}
+
 template <int PREC, bool DAG, bool RED, int GROUP>
 __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__ gauge, FieldRef in,
                                                 FieldRef out, double kappa_d, RedArgs red,
@@ -153,25 +177,11 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
     if (live && gate.st && !gate.st[rhs].active) live = false;
     double nrm = 0.0;
     if (live) {
-        const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
-        const int x = site % Lx;
-        int q = site / Lx;
-        const int y = q % Ly;
-        q /= Ly;
-        const int z = q % Lz;
-        const int t = q / Lz;
-        const int sx = 1, sy = Lx, sz = Lx * Ly, st = Lx * Ly * Lz;
-        const int xp = x == Lx - 1 ? site - (Lx - 1) * sx : site + sx;
-        const int xm = x == 0 ? site + (Lx - 1) * sx : site - sx;
-        const int yp = y == Ly - 1 ? site - (Ly - 1) * sy : site + sy;
-        const int ym = y == 0 ? site + (Ly - 1) * sy : site - sy;
-        const int zp = z == Lz - 1 ? site - (Lz - 1) * sz : site + sz;
-        const int zm = z == 0 ? site + (Lz - 1) * sz : site - sz;
-        const int tp = t == Lt - 1 ? site - (Lt - 1) * st : site + st;
-        const int tm = t == 0 ? site + (Lt - 1) * st : site - st;
-        const bool neg_tp = g.antiperiodic && t == Lt - 1;
-        const bool neg_tm = g.antiperiodic && t == 0;
-        const int V = g.V;
+        const Nbrs nb = neighbours(g, site);
+        const int xp = nb.xp, xm = nb.xm, yp = nb.yp, ym = nb.ym;
+        const int zp = nb.zp, zm = nb.zm, tp = nb.tp, tm = nb.tm;
+        const bool neg_tp = g.antiperiodic && nb.cross_tp;
+        const bool neg_tm = g.antiperiodic && nb.cross_tm;
 
         cx<R> acc[12];
 #pragma unroll
@@ -184,21 +194,21 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
         // memory-level parallelism).
 #define WD_HOP_FENCE(k) \
     if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
-        hop<0, SF, false, PREC>(gauge, V, in, xp * nrhs + rhs, site, false, acc);
+        hop<0, SF, false, PREC>(gauge, in, xp * nrhs + rhs, site, false, acc);
         WD_HOP_FENCE(1);
-        hop<0, SB, true, PREC>(gauge, V, in, xm * nrhs + rhs, xm, false, acc);
+        hop<0, SB, true, PREC>(gauge, in, xm * nrhs + rhs, xm, false, acc);
         WD_HOP_FENCE(2);
-        hop<1, SF, false, PREC>(gauge, V, in, yp * nrhs + rhs, site, false, acc);
+        hop<1, SF, false, PREC>(gauge, in, yp * nrhs + rhs, site, false, acc);
         WD_HOP_FENCE(3);
-        hop<1, SB, true, PREC>(gauge, V, in, ym * nrhs + rhs, ym, false, acc);
+        hop<1, SB, true, PREC>(gauge, in, ym * nrhs + rhs, ym, false, acc);
         WD_HOP_FENCE(4);
-        hop<2, SF, false, PREC>(gauge, V, in, zp * nrhs + rhs, site, false, acc);
+        hop<2, SF, false, PREC>(gauge, in, zp * nrhs + rhs, site, false, acc);
         WD_HOP_FENCE(5);
-        hop<2, SB, true, PREC>(gauge, V, in, zm * nrhs + rhs, zm, false, acc);
+        hop<2, SB, true, PREC>(gauge, in, zm * nrhs + rhs, zm, false, acc);
         WD_HOP_FENCE(6);
-        hop<3, SF, false, PREC>(gauge, V, in, tp * nrhs + rhs, site, neg_tp, acc);
+        hop<3, SF, false, PREC>(gauge, in, tp * nrhs + rhs, site, neg_tp, acc);
         WD_HOP_FENCE(7);
-        hop<3, SB, true, PREC>(gauge, V, in, tm * nrhs + rhs, tm, neg_tm, acc);
+        hop<3, SB, true, PREC>(gauge, in, tm * nrhs + rhs, tm, neg_tm, acc);
         WD_HOP_FENCE(8);
 #undef WD_HOP_FENCE
 
@@ -215,6 +225,129 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
     if (RED) reduce_block(nrm, red.partials, nrhs);
 }
 
+
+// Time-marching stencil (nrhs == 1).  One workgroup per brick column and
+// chunk of time slices, one lane per brick site.  The workgroup steps
+// through its time slices together, so the x/y/z neighbours a lane reads
+// were fetched by its neighbour lanes moments earlier, and the backward t
+// hop U_t(x, t-1)^dag (1 -+ gamma_t) psi(x, t-1) is carried from the previous
+// slice in registers instead of being reloaded.  Blocks are ordered chunk
+// major, so each XCD's contiguous block run covers one band of time slices
+// of many neighbouring columns (their shared brick faces stay in its L2).
+template <int PREC, bool DAG, bool RED, int GROUP>
+__global__ void __launch_bounds__(256) k_dslash_tm(Geom g, const void *__restrict__ gauge,
+                                                   FieldRef in, FieldRef out, double kappa_d,
+                                                   RedArgs red, Gate gate, int tchunk,
+                                                   int ncols) {
+    using R = typename Spinor<PREC>::R;
+    if (gate.batch && gate.batch->n_active == 0) return;  // grid-uniform
+    const int b = logical_block();
+    const int chunk = b / ncols;
+    const int col = b - chunk * ncols;
+    const int Lt = g.L[3];
+    const int t0 = chunk * tchunk;
+    const int t1 = t0 + tchunk < Lt ? t0 + tchunk : Lt;
+    const bool live = !gate.st || gate.st[0].active;  // uniform (one rhs)
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const R kappa = (R)kappa_d;
+    double nrm = 0.0;
+    if (live) {
+        const int base = col * Lt * g.bvol + (int)threadIdx.x;
+        // carried backward t hop for the first slice: from t0 - 1
+        cx<R> cw0[3], cw1[3];
+        {
+            const int tprev = t0 == 0 ? Lt - 1 : t0 - 1;
+            const int ip = base + tprev * g.bvol;
+            cx<R> p[12];
+            Spinor<PREC>::load(in, ip, p);
+            cx<R> h0[3], h1[3];
+            project<3, SB>(p, h0, h1);
+            const R sg = (g.antiperiodic && t0 == 0) ? R(-1) : R(1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                h0[c] = scale(sg, h0[c]);
+                h1[c] = scale(sg, h1[c]);
+            }
+            cx<R> u[9];
+            Link<PREC>::load(gauge, 3, ip, u);
+            su3_mul<true>(u, h0, cw0);
+            su3_mul<true>(u, h1, cw1);
+        }
+        for (int t = t0; t < t1; ++t) {
+            const int i = base + t * g.bvol;
+            const Nbrs nb = neighbours(g, i);
+            cx<R> acc[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+#define WD_HOP_FENCE(k) \
+    if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
+            hop<0, SF, false, PREC>(gauge, in, nb.xp, i, false, acc);
+            WD_HOP_FENCE(1);
+            hop<0, SB, true, PREC>(gauge, in, nb.xm, nb.xm, false, acc);
+            WD_HOP_FENCE(2);
+            hop<1, SF, false, PREC>(gauge, in, nb.yp, i, false, acc);
+            WD_HOP_FENCE(3);
+            hop<1, SB, true, PREC>(gauge, in, nb.ym, nb.ym, false, acc);
+            WD_HOP_FENCE(4);
+            hop<2, SF, false, PREC>(gauge, in, nb.zp, i, false, acc);
+            WD_HOP_FENCE(5);
+            hop<2, SB, true, PREC>(gauge, in, nb.zm, nb.zm, false, acc);
+            WD_HOP_FENCE(6);
+            cx<R> ut[9];
+            Link<PREC>::load(gauge, 3, i, ut);
+            hop_u<3, SF, false, PREC>(ut, in, nb.tp, g.antiperiodic && nb.cross_tp, acc);
+            WD_HOP_FENCE(7);
+#undef WD_HOP_FENCE
+            accumulate<3, SB>(cw0, cw1, acc);
+            cx<R> c[12];
+            Spinor<PREC>::load(in, i, c);
+            // carry for slice t + 1 (never crosses the boundary inside a chunk)
+            {
+                cx<R> h0[3], h1[3];
+                project<3, SB>(c, h0, h1);
+                su3_mul<true>(ut, h0, cw0);
+                su3_mul<true>(ut, h1, cw1);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                c[k] = c[k] - scale(kappa, acc[k]);
+                if (RED) nrm += (double)c[k].re * (double)c[k].re + (double)c[k].im * (double)c[k].im;
+            }
+            Spinor<PREC>::store(out, i, c);
+            __syncthreads();  // keep the brick in step
+        }
+    }
+    if (RED) reduce_block(nrm, red.partials, 1);
+}
+
+// chunks of time slices for the marching stencil: enough workgroups to fill
+// the chip (a multiple of 8 chunks where the extent allows), WD_TCHUNK
+// overrides the chunk length (tuning)
+static int tm_chunk(const Geom &g) {
+    static const int env = [] {
+        const char *e = getenv("WD_TCHUNK");
+        return e ? atoi(e) : 0;
+    }();
+    const int Lt = g.L[3];
+    if (env > 0) return env < Lt ? env : Lt;
+    const int ncols = g.V / (Lt * g.bvol);
+    int nch = 8;
+    while (nch < Lt && ncols * nch < 2048) nch += 8;
+    if (nch > Lt) nch = Lt;
+    return (Lt + nch - 1) / nch;
+}
+
+static bool use_tm(const Geom &g, int nrhs) {
+    return nrhs == 1 && g.bvol % 64 == 0 && g.bvol <= 256;
+}
+
+// WD_SITE_KERNEL=1 forces the one-lane-per-entry stencil everywhere (tuning)
+static const bool g_force_site_kernel = [] {
+    const char *e = getenv("WD_SITE_KERNEL");
+    return e && atoi(e) != 0;
+}();
+
 // hops per scheduling group (see k_dslash)
 template <int PREC>
 struct HopGroup {
@@ -222,8 +355,36 @@ struct HopGroup {
 };
 
 template <int PREC>
+static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
+                      FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
+    const int tch = tm_chunk(g);
+    const int ncols = g.V / (g.L[3] * g.bvol);
+    const int nb = ncols * ((g.L[3] + tch - 1) / tch);
+    const int bs = g.bvol;
+    constexpr int G = HopGroup<PREC>::value;
+    RedArgs r{};
+    if (red) r = *red;
+    if (dagger) {
+        if (red)
+            hipLaunchKernelGGL((k_dslash_tm<PREC, true, true, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+        else
+            hipLaunchKernelGGL((k_dslash_tm<PREC, true, false, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+    } else {
+        if (red)
+            hipLaunchKernelGGL((k_dslash_tm<PREC, false, true, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+        else
+            hipLaunchKernelGGL((k_dslash_tm<PREC, false, false, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+    }
+    if (red) launch_finalize(r, nb, gate.batch != nullptr, s);
+}
+
+template <int PREC>
 static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                         FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
+    if (use_tm(g, in.nrhs) && !g_force_site_kernel) {
+        launch_tm<PREC>(g, gauge, kappa, dagger, in, out, red, gate, s);
+        return;
+    }
     const int bs = block_for_nrhs(in.nrhs);
     const int nb = blocks_for(in.n, bs);
     RedArgs r{};

@@ -5,6 +5,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -44,12 +46,64 @@ FieldRef carve(char *&cursor, int prec, int nrhs, int V) {
     f.nrhs = nrhs;
     f.n = V * nrhs;
     f.data = cursor;
-    cursor += (size_t)planes_for(prec) * 16u * (size_t)f.n;
-    if (prec == WD_F16) {
-        f.scale = (float *)cursor;
-        cursor += ((4u * (size_t)f.n + 255u) / 256u) * 256u;
-    }
+    cursor += spinor_bytes(prec, f.n);
     return f;
+}
+
+// Brick extents.  Preferred: tx * ty * tz a multiple of 64 and at most 256
+// (one brick per workgroup for the time-marching stencil), whole x rows
+// first (measured fastest at 48^3 x 96: full rows keep the x neighbours and
+// the backward x links inside the brick), then the largest volume.  Lattices too small
+// for that take whole x-rows with the largest y/z divisors up to 8 and 4.
+// WD_BRICK="tx,ty,tz" overrides the choice (tuning).
+static int largest_divisor_le(int n, int cap) {
+    for (int d = cap < n ? cap : n; d >= 1; --d)
+        if (n % d == 0) return d;
+    return 1;
+}
+
+void choose_bricks(Geom &g) {
+    int bx = 0, by = 0, bz = 0, best = 0;
+    for (int a = 1; a <= g.L[0]; ++a) {
+        if (g.L[0] % a) continue;
+        for (int b = 1; b <= g.L[1]; ++b) {
+            if (g.L[1] % b) continue;
+            for (int c = 1; c <= g.L[2]; ++c) {
+                if (g.L[2] % c) continue;
+                const int v = a * b * c;
+                if (v > 256 || v % 64) continue;
+                // prefer whole x rows, then volume, then y over z
+                const int score = (a == g.L[0] ? (1 << 24) : 0) + v * 4096 + a * 64 + b;
+                if (score > best) {
+                    best = score;
+                    bx = a;
+                    by = b;
+                    bz = c;
+                }
+            }
+        }
+    }
+    if (!best) {
+        bx = g.L[0];
+        by = largest_divisor_le(g.L[1], 8);
+        bz = largest_divisor_le(g.L[2], 4);
+    }
+    if (const char *e = getenv("WD_BRICK")) {
+        int a = 0, b = 0, c = 0;
+        if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && c >= 1 &&
+            g.L[0] % a == 0 && g.L[1] % b == 0 && g.L[2] % c == 0) {
+            bx = a;
+            by = b;
+            bz = c;
+        }
+    }
+    g.tx = bx;
+    g.ty = by;
+    g.tz = bz;
+    g.ncx = g.L[0] / bx;
+    g.ncy = g.L[1] / by;
+    g.ncz = g.L[2] / bz;
+    g.bvol = bx * by * bz;
 }
 
 void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err) {
@@ -169,6 +223,7 @@ int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out
     for (int m = 0; m < 4; ++m) lat->g.L[m] = dims[m];
     lat->g.V = (int)V;
     lat->g.antiperiodic = (bc_flags & WD_BC_ANTIPERIODIC_T) ? 1 : 0;
+    choose_bricks(lat->g);
     *out = lat;
     return WD_OK;
 }
@@ -212,7 +267,7 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
                         hipGetErrorString(he));
         lat->gauge[WD_F64] = p;
     }
-    launch_pack_gauge_f64(U, lat->gauge[WD_F64], lat->g.V, s);
+    launch_pack_gauge_f64(U, lat->gauge[WD_F64], lat->g, s);
     for (int p = 1; p < 3; ++p)
         if (lat->gauge[p]) launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], p, lat->g.V, s);
     WD_HIP_CHECK(hipGetLastError());
@@ -227,7 +282,7 @@ int wd_field_create(wd_lattice *lat, int prec, int nrhs, wd_field **out) {
     if (nrhs < 1 || nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", nrhs);
     wd_field *f = new (std::nothrow) wd_field();
     if (!f) return fail(WD_ERR_NOMEM, "host allocation failed");
-    size_t bytes = spinor_bytes(prec, (int64_t)lat->g.V * nrhs) + 256;
+    size_t bytes = spinor_bytes(prec, (int64_t)lat->g.V * nrhs);
     hipError_t he = hipMalloc(&f->mem, bytes);
     if (he != hipSuccess) {
         delete f;
@@ -251,14 +306,14 @@ int wd_field_destroy(wd_field *f) {
 
 int wd_field_import(wd_field *f, const double *canon, void *stream) {
     if (!f || !canon) return fail(WD_ERR_ARG, "null argument");
-    launch_import(canon, f->ref, (hipStream_t)stream);
+    launch_import(canon, f->ref, f->lat->g, (hipStream_t)stream);
     WD_HIP_CHECK(hipGetLastError());
     return WD_OK;
 }
 
 int wd_field_export(const wd_field *f, double *canon, void *stream) {
     if (!f || !canon) return fail(WD_ERR_ARG, "null argument");
-    launch_export(f->ref, canon, (hipStream_t)stream);
+    launch_export(f->ref, canon, f->lat->g, (hipStream_t)stream);
     WD_HIP_CHECK(hipGetLastError());
     return WD_OK;
 }
@@ -304,9 +359,9 @@ int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, cons
     FieldRef a = carve(cur, prec, nrhs, V);
     cur = (char *)mem + one;
     FieldRef b = carve(cur, prec, nrhs, V);
-    launch_import(in, a, s);
+    launch_import(in, a, lat->g, s);
     dslash(lat, g, kappa, dagger, a, b, nullptr, Gate{nullptr, nullptr}, s);
-    launch_export(b, out, s);
+    launch_export(b, out, lat->g, s);
     (void)hipFreeAsync(mem, s);
     WD_HIP_CHECK(hipGetLastError());
     return WD_OK;

@@ -152,11 +152,11 @@ int Solve::start() {
     const double k = p_.kappa;
     const Gate none{nullptr, nullptr};
     launch_init_state(st_, batch_, p_.nrhs, s_);
-    launch_import(b_, b64_, s_);
+    launch_import(b_, b64_, lat_->g, s_);
     RedArgs rb = red(RED_B0);
     dslash(lat_, gauge64_, k, 1, b64_, bp_, &rb, none, s_);  // b' = D^dag b, |b'|^2
     if (p_.x0_given)
-        launch_import(x_, x64_, s_);
+        launch_import(x_, x64_, lat_->g, s_);
     else
         launch_zero(x64_, s_);
     launch_zero(xl_, s_);
@@ -203,7 +203,7 @@ void Solve::enqueue_finish() {
     launch_residual(ax64_, b64_, t64_, ra, s_);  // |b - D x|^2
     RedArgs rb = red(RED_AUX2);
     launch_norm(b64_, rb, s_);                  // |b|^2
-    launch_export(x64_, x_, s_);
+    launch_export(x64_, x_, lat_->g, s_);
     final_slot_ = 0;
     (void)hipMemcpyAsync(h_st_, st_, sizeof(RhsState) * p_.nrhs, hipMemcpyDeviceToHost, s_);
     (void)hipEventRecord(final_ev_, s_);

@@ -13,51 +13,135 @@ namespace wd {
 
 // ------------------------------------------------------------------ layout
 //
-// Spinor fields are site-major structure-of-arrays.  An entry index
-// i = s * nrhs + rhs runs over sites and right-hand sides (rhs fastest), and
-// the 12 complex components k = 3 * spin + colour are spread over planes of
-// 16-byte vectors so that one lane moves 16 bytes per load:
-//   WD_F64: 12 planes of double2 (one complex per plane)
-//   WD_F32:  6 planes of float4  (components 2j, 2j+1 in plane j)
-//   WD_F16:  3 planes of 4 x half2 (components 4j..4j+3 in plane j) plus one
-//            float plane holding the site scale (max |real or imag part|)
-// Plane p of a field with n entries starts at byte p * n * 16.
+// Site order.  Internal fields do not use the canonical lexicographic order.
+// The lattice is cut into bricks of tx * ty * tz sites (divisors of Lx, Ly,
+// Lz); a brick column is the run of Lt bricks that share the same (x, y, z)
+// ranges, one per time slice.  Internal site index
+//     i = ((column * Lt + t) * bvol) + x % tx + tx * (y % ty + ty * (z % tz)),
+//     column = x / tx + ncx * (y / ty + ncy * (z / tz)).
+// A sweep in this order marches t inside each column, so a site's t-1
+// neighbour was touched one brick (bvol sites) earlier; x, y and z
+// neighbours are inside the brick except on its faces.
 //
-// Gauge links: for each direction mu a group of planes indexed by site:
-//   F64-18: 9 planes of double2 (entry a*3+b of U_mu(s))
-//   F32-12: 3 planes of float4  (rows 0 and 1: entries 0..5, two per plane)
-//   F16-12: 3 planes of 2 x half2 (rows 0 and 1, two entries per plane)
+// Entries.  Spinor fields hold nrhs right-hand sides; entry e = i * nrhs + rhs.
+//
+// Tiles.  Every field is an array of tiles of 64 consecutive entries (sites
+// for links).  Inside a tile each component plane is one contiguous run of
+// 64 elements of 16 bytes (8 for binary16 links), so a wave of 64 lanes moves
+// one aligned 1 KiB block per load and the planes of neighbouring entries
+// never alias in the caches:
+//   spinor WD_F64: 12 planes of double2 (complex component k = 3 spin + colour)
+//          WD_F32:  6 planes of float4  (components 2j, 2j+1 in plane j)
+//          WD_F16:  3 planes of 4 x half2 (components 4j..4j+3) followed by
+//                   64 float scales (the entry's max |real or imag part|)
+//   links  F64-18: 36 planes of double2 (plane 9 mu + 3 a + b of U_mu)
+//          F32-12: 12 planes of float4  (plane 3 mu + j: entries 2j, 2j+1 of
+//                  rows 0 and 1)
+//          F16-12: 12 planes of 2 x half2 (same entries, 8-byte elements)
 // Row 2 of the 12-real forms is rebuilt as conj(row0 x row1), which is exact
 // for special unitary links; the antiperiodic boundary sign is therefore
 // never folded into stored links but applied to the hop result.
 
 constexpr int kNComp = 12;  // 4 spins x 3 colours
+constexpr int kTile = 64;   // entries per tile
 
-inline int planes_for(int prec) { return prec == WD_F64 ? 12 : (prec == WD_F32 ? 6 : 3); }
+inline size_t tiles_of(int64_t n) { return (size_t)((n + kTile - 1) / kTile); }
 
-inline size_t spinor_bytes(int prec, int64_t n) {
-    size_t b = (size_t)planes_for(prec) * 16u * (size_t)n;
-    if (prec == WD_F16) b += 4u * (size_t)n;
-    return b;
+inline size_t spinor_tile_bytes(int prec) {
+    return prec == WD_F64 ? 12u * 1024u : (prec == WD_F32 ? 6u * 1024u : 3u * 1024u + 256u);
 }
 
-inline size_t gauge_bytes(int prec, int64_t V) {
-    size_t per_link = prec == WD_F64 ? 144u : (prec == WD_F32 ? 48u : 24u);
-    return (size_t)4 * per_link * (size_t)V;
+inline size_t spinor_bytes(int prec, int64_t n) { return tiles_of(n) * spinor_tile_bytes(prec); }
+
+inline size_t gauge_tile_bytes(int prec) {
+    return prec == WD_F64 ? 36u * 1024u : (prec == WD_F32 ? 12u * 1024u : 12u * 512u);
 }
+
+inline size_t gauge_bytes(int prec, int64_t V) { return tiles_of(V) * gauge_tile_bytes(prec); }
 
 struct Geom {
-    int L[4];
+    int L[4];  // Lx, Ly, Lz, Lt
     int V;
     int antiperiodic;
+    int tx, ty, tz;     // brick extents (divisors of Lx, Ly, Lz)
+    int ncx, ncy, ncz;  // Lx / tx, Ly / ty, Lz / tz
+    int bvol;           // tx * ty * tz
 };
+
+// internal site index -> lattice coordinates
+__host__ __device__ inline void coords_of(const Geom &g, int i, int &x, int &y, int &z, int &t) {
+    const int local = i % g.bvol;
+    const int ct = i / g.bvol;
+    t = ct % g.L[3];
+    int col = ct / g.L[3];
+    const int bx = col % g.ncx;
+    col /= g.ncx;
+    const int by = col % g.ncy, bz = col / g.ncy;
+    const int xl = local % g.tx;
+    const int q = local / g.tx;
+    x = bx * g.tx + xl;
+    y = by * g.ty + q % g.ty;
+    z = bz * g.tz + q / g.ty;
+}
+
+// lattice coordinates -> internal site index
+__host__ __device__ inline int index_of(const Geom &g, int x, int y, int z, int t) {
+    const int bx = x / g.tx, by = y / g.ty, bz = z / g.tz;
+    const int col = bx + g.ncx * (by + g.ncy * bz);
+    return (col * g.L[3] + t) * g.bvol + (x - bx * g.tx) +
+           g.tx * ((y - by * g.ty) + g.ty * (z - bz * g.tz));
+}
+
+// canonical (lexicographic, x fastest) site of lattice coordinates
+__host__ __device__ inline int lex_of(const Geom &g, int x, int y, int z, int t) {
+    return x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
+}
+
+// the eight neighbours of internal site i (x+, x-, y+, y-, z+, z-, t+, t-)
+// and whether the t hops cross the time boundary
+struct Nbrs {
+    int xp, xm, yp, ym, zp, zm, tp, tm;
+    bool cross_tp, cross_tm;
+};
+
+// one spatial direction: local offset inside the brick, or a step to the
+// neighbouring column (periodic in the column index) on a brick face
+__host__ __device__ inline void nbr_dir(int i, int l, int tl, int b, int nb, int lstride,
+                                        int cstride, int &plus, int &minus) {
+    plus = l < tl - 1 ? i + lstride
+                      : i - (tl - 1) * lstride + (b == nb - 1 ? -(nb - 1) : 1) * cstride;
+    minus = l > 0 ? i - lstride : i + (tl - 1) * lstride + (b == 0 ? (nb - 1) : -1) * cstride;
+}
+
+__host__ __device__ inline Nbrs neighbours(const Geom &g, int i) {
+    const int Lt = g.L[3];
+    const int local = i % g.bvol;
+    const int ct = i / g.bvol;
+    const int t = ct % Lt;
+    int col = ct / Lt;
+    const int bx = col % g.ncx;
+    col /= g.ncx;
+    const int by = col % g.ncy, bz = col / g.ncy;
+    const int xl = local % g.tx;
+    const int q = local / g.tx;
+    const int yl = q % g.ty, zl = q / g.ty;
+    const int cx = Lt * g.bvol;  // index stride of one column
+    Nbrs n;
+    nbr_dir(i, xl, g.tx, bx, g.ncx, 1, cx, n.xp, n.xm);
+    nbr_dir(i, yl, g.ty, by, g.ncy, g.tx, g.ncx * cx, n.yp, n.ym);
+    nbr_dir(i, zl, g.tz, bz, g.ncz, g.tx * g.ty, g.ncx * g.ncy * cx, n.zp, n.zm);
+    n.tp = t == Lt - 1 ? i - (Lt - 1) * g.bvol : i + g.bvol;
+    n.tm = t == 0 ? i + (Lt - 1) * g.bvol : i - g.bvol;
+    n.cross_tp = t == Lt - 1;
+    n.cross_tm = t == 0;
+    return n;
+}
 
 struct FieldRef {
     int prec;
     int nrhs;
-    int n;        // V * nrhs entries per plane
-    void *data;   // planes
-    float *scale; // WD_F16 only (n floats)
+    int n;       // V * nrhs entries
+    void *data;  // tiles
 };
 
 // ------------------------------------------------------------------ solver state
@@ -145,11 +229,14 @@ inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 // ------------------------------------------------------------------ launchers
 // (defined in the .hip files; all stream-ordered, no host synchronisation)
 
-void launch_pack_gauge_f64(const double *canon, void *g64, int V, hipStream_t s);
+// canonical float64 links -> F64-18 tiles (brick order)
+void launch_pack_gauge_f64(const double *canon, void *g64, const Geom &g, hipStream_t s);
+// F64-18 tiles -> 12-real F32 or F16 tiles
 void launch_gauge_lo(const void *g64, void *glo, int prec, int V, hipStream_t s);
 
-void launch_import(const double *canon, FieldRef f, hipStream_t s);
-void launch_export(FieldRef f, double *canon, hipStream_t s);
+// canonical [rhs][V][12] float64 <-> field (format conversion + reorder)
+void launch_import(const double *canon, FieldRef f, const Geom &g, hipStream_t s);
+void launch_export(FieldRef f, double *canon, const Geom &g, hipStream_t s);
 // dst = src with a format conversion (same nrhs); gated rhs only
 void launch_convert(FieldRef src, FieldRef dst, Gate gate, hipStream_t s);
 void launch_zero(FieldRef f, hipStream_t s);

@@ -81,3 +81,10 @@ def test_apply_rejects_bad_args_before_gpu():
     # no gauge yet: refused before any device work
     assert wd.lib.wd_apply(lat.handle, 0.1, 0, 0, 1, a, b, None) == wd.WD_ERR_NOGAUGE
     lat.close()
+
+
+def test_no_unresolved_library_symbols():
+    out = subprocess.run(["nm", "-D", "--undefined-only", wd.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    own = [line for line in out.splitlines() if "_ZN2wd" in line or " wd_" in line]
+    assert not own, own
