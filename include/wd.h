@@ -119,11 +119,13 @@ int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, cons
              double *out, void *stream);
 
 /* --------------------------------------------------- fields (internal layout)
- * A wd_field holds nrhs spinors in the site-major structure-of-arrays layout
- * the kernels use: 12 planes (spin*3+colour) of complex numbers, each plane
- * indexed by s*nrhs + rhs (plus one float32 scale plane for WD_F16).  Used to
- * time the stencil on resident data and to chain operators without the
- * canonical round trip. */
+ * A wd_field holds nrhs spinors in the layout the kernels use: sites in
+ * brick-column order (bricks of the lattice, each column marching in t),
+ * entries site * nrhs + rhs grouped in tiles of 64, and inside a tile one
+ * contiguous run per spin-colour component (plus per-entry float32 scales
+ * for WD_F16).  The layout is private; import/export convert from/to the
+ * canonical order.  Fields time the stencil on resident data and chain
+ * operators without the canonical round trip. */
 int wd_field_create(wd_lattice *lat, int prec, int nrhs, wd_field **out);
 int wd_field_destroy(wd_field *f);
 /* canonical float64 [rhs][V][24] (device) -> field, rounding to its format */
@@ -155,6 +157,7 @@ typedef struct {
     double true_rel_resid;    /* ||D^dag b - D^dag D x|| / ||D^dag b|| in FP64 */
     double rel_resid_D;       /* ||b - D x|| / ||b|| in FP64 */
     double seconds;           /* wall time of the solve (submit to completion when served) */
+    double queued_seconds;    /* served: submission to admission; 0 for wd_cg_solve */
 } wd_solve_info;
 
 /* Solve D^dag D x = D^dag b for nrhs right-hand sides (blocking; returns when
@@ -182,8 +185,10 @@ typedef struct {
 int wd_server_create(const wd_server_config *cfg, wd_server **out);
 
 /* Queue a solve (non-blocking).  Same arguments as wd_cg_solve; the lattice
- * must have its gauge set and must outlive the request.  *ticket identifies
- * it.  WD_ERR_NOMEM if the request alone exceeds the whole budget. */
+ * must have its gauge set and must outlive the request, and b must already
+ * hold the source on the device (the server reads it from its own stream,
+ * unordered with the caller's streams).  *ticket identifies the request.
+ * WD_ERR_NOMEM if the request alone exceeds the whole budget. */
 int wd_submit(wd_server *s, wd_lattice *lat, const wd_solve_params *p, const double *b,
               double *x, uint64_t *ticket);
 

@@ -59,7 +59,8 @@ class wd_solve_params(ctypes.Structure):
 class wd_solve_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("true_rel_resid", ctypes.c_double),
-                ("rel_resid_D", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_resid_D", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("queued_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -327,6 +328,8 @@ class Server:
                max_iter=20000, reliable_max_iter=50, reliable_delta=0.1) -> int:
         p = make_params(kappa, tol, max_iter, prec, nrhs, reliable_max_iter, reliable_delta)
         n = lattice.volume * 24 * nrhs
+        # the server reads b on its own stream: make the caller's writes visible
+        _torch().cuda.current_stream().synchronize()
         t = ctypes.c_uint64()
         _check(lib.wd_submit(self.handle, lattice.handle, ctypes.byref(p), _dptr(b, n, "b"),
                              _dptr(x, n, "x"), ctypes.byref(t)))

@@ -321,25 +321,13 @@ __global__ void __launch_bounds__(256) k_dslash_tm(Geom g, const void *__restric
     if (RED) reduce_block(nrm, red.partials, 1);
 }
 
-// chunks of time slices for the marching stencil: enough workgroups to fill
-// the chip (a multiple of 8 chunks where the extent allows), WD_TCHUNK
-// overrides the chunk length (tuning)
+// WD_TCHUNK overrides the marching stencil's chunk length (tuning)
 static int tm_chunk(const Geom &g) {
     static const int env = [] {
         const char *e = getenv("WD_TCHUNK");
         return e ? atoi(e) : 0;
     }();
-    const int Lt = g.L[3];
-    if (env > 0) return env < Lt ? env : Lt;
-    const int ncols = g.V / (Lt * g.bvol);
-    int nch = 8;
-    while (nch < Lt && ncols * nch < 2048) nch += 8;
-    if (nch > Lt) nch = Lt;
-    return (Lt + nch - 1) / nch;
-}
-
-static bool use_tm(const Geom &g, int nrhs) {
-    return nrhs == 1 && g.bvol % 64 == 0 && g.bvol <= 256;
+    return tm_chunk_len(g, env);
 }
 
 // WD_SITE_KERNEL=1 forces the one-lane-per-entry stencil everywhere (tuning)
@@ -359,7 +347,7 @@ static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger
                       FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
     const int tch = tm_chunk(g);
     const int ncols = g.V / (g.L[3] * g.bvol);
-    const int nb = ncols * ((g.L[3] + tch - 1) / tch);
+    const int nb = tm_blocks(g, tch);
     const int bs = g.bvol;
     constexpr int G = HopGroup<PREC>::value;
     RedArgs r{};
@@ -381,7 +369,11 @@ static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger
 template <int PREC>
 static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                         FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
-    if (use_tm(g, in.nrhs) && !g_force_site_kernel) {
+    // the marching stencil needs one partial per workgroup: use it only when
+    // the caller's partial buffer holds them (it always does when sized by
+    // reduce_partials_cap)
+    if (tm_eligible(g, in.nrhs) && !g_force_site_kernel &&
+        (!red || tm_blocks(g, tm_chunk(g)) <= red->partials_cap)) {
         launch_tm<PREC>(g, gauge, kappa, dagger, in, out, red, gate, s);
         return;
     }

@@ -270,7 +270,7 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
     launch_pack_gauge_f64(U, lat->gauge[WD_F64], lat->g, s);
     for (int p = 1; p < 3; ++p)
         if (lat->gauge[p]) launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], p, lat->g.V, s);
-    WD_HIP_CHECK(hipGetLastError());
+    WD_LAUNCH_CHECK();
     WD_HIP_CHECK(hipStreamSynchronize(s));
     lat->has_gauge = true;
     return WD_OK;
@@ -307,14 +307,14 @@ int wd_field_destroy(wd_field *f) {
 int wd_field_import(wd_field *f, const double *canon, void *stream) {
     if (!f || !canon) return fail(WD_ERR_ARG, "null argument");
     launch_import(canon, f->ref, f->lat->g, (hipStream_t)stream);
-    WD_HIP_CHECK(hipGetLastError());
+    WD_LAUNCH_CHECK();
     return WD_OK;
 }
 
 int wd_field_export(const wd_field *f, double *canon, void *stream) {
     if (!f || !canon) return fail(WD_ERR_ARG, "null argument");
     launch_export(f->ref, canon, f->lat->g, (hipStream_t)stream);
-    WD_HIP_CHECK(hipGetLastError());
+    WD_LAUNCH_CHECK();
     return WD_OK;
 }
 
@@ -332,7 +332,7 @@ int wd_dslash(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_
     void *g = gauge_for(lat, in->prec, s, &err);
     if (!g) return err;
     dslash(lat, g, kappa, dagger, in->ref, out->ref, nullptr, Gate{nullptr, nullptr}, s);
-    WD_HIP_CHECK(hipGetLastError());
+    WD_LAUNCH_CHECK();
     return WD_OK;
 }
 
@@ -363,7 +363,7 @@ int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, cons
     dslash(lat, g, kappa, dagger, a, b, nullptr, Gate{nullptr, nullptr}, s);
     launch_export(b, out, lat->g, s);
     (void)hipFreeAsync(mem, s);
-    WD_HIP_CHECK(hipGetLastError());
+    WD_LAUNCH_CHECK();
     return WD_OK;
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <atomic>
+#include <cmath>
 #include <cstdio>
 #include <deque>
 #include <mutex>
@@ -38,6 +39,18 @@ int fail(int code, const char *fmt, ...);
             return ::wd::fail(WD_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// hipGetLastError reports the last status of any runtime call on this thread,
+// including hipErrorNotReady from an event or stream query (ours or the
+// caller's); that status is not a launch failure.
+inline bool launch_failed() {
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess && e != hipErrorNotReady;
+}
+#define WD_LAUNCH_CHECK()                                                      \
+    do {                                                                       \
+        if (::wd::launch_failed()) return ::wd::fail(WD_ERR_HIP, "kernel launch failed"); \
+    } while (0)
+
 bool valid_prec(int p);
 // packed gauge form for a precision, building the 12-real forms on first use
 // (enqueued on stream s).  Returns nullptr and sets the error on failure.
@@ -52,14 +65,28 @@ void choose_bricks(Geom &g);
 
 // ------------------------------------------------------------------ solve
 
+// Pinned status buffers and events a solve polls through.  A server keeps
+// one per slot so that admitting and retiring requests allocates no pinned
+// memory; a blocking solve creates its own.
+struct SlotRes {
+    static constexpr int kSlots = 6;
+    RhsState *h_st = nullptr;       // kSlots * 12 (one ring slot per status read)
+    BatchState *h_batch = nullptr;  // kSlots
+    hipEvent_t ev[kSlots] = {};
+    hipEvent_t final_ev = nullptr;
+    int create();
+    void destroy();
+};
+
 class Solve {
   public:
     Solve(wd_lattice *lat, const wd_solve_params &p, const double *b, double *x);
     ~Solve();
     static int validate(wd_lattice *lat, const wd_solve_params *p);
     static size_t footprint(const wd_lattice *lat, const wd_solve_params &p);
-    // allocate device and pinned memory and bind a stream; no work enqueued
-    int setup(hipStream_t stream);
+    // allocate the workspace (stream-ordered) and bind a stream and status
+    // buffers (res == nullptr: own ones); no work enqueued
+    int setup(hipStream_t stream, SlotRes *res = nullptr);
     // enqueue the start sequence (source prep and first residual)
     int start();
     // advance the state machine; block: wait for device status.  Returns
@@ -69,6 +96,8 @@ class Solve {
     int result() const { return result_; }
     size_t bytes() const { return bytes_; }
     int nrhs() const { return p_.nrhs; }
+    // iterations enqueued per status read (default chosen from the volume)
+    void set_chunk(int c) { chunk_ = c < 1 ? 1 : c; }
     double seconds = 0.0;
 
   private:
@@ -99,18 +128,19 @@ class Solve {
     RhsState *st_ = nullptr;
     BatchState *batch_ = nullptr;
     double *partials_ = nullptr;
+    int partials_cap_ = 0;
     SolveCtl ctl_{};
     // pinned status ring
-    static constexpr int kSlots = 6;
-    RhsState *h_st_ = nullptr;      // kSlots * nrhs
-    BatchState *h_batch_ = nullptr; // kSlots
-    std::vector<hipEvent_t> events_;
+    static constexpr int kSlots = SlotRes::kSlots;
+    SlotRes own_{};
+    SlotRes *res_ = nullptr;
+    RhsState *h_st_ = nullptr;       // res_->h_st
+    BatchState *h_batch_ = nullptr;  // res_->h_batch
     std::deque<Pending> pending_;
     int next_slot_ = 0;
     int epoch_ = 0;
     int phase_ = 0;  // 0 running, 1 finishing, 2 done
     hipEvent_t final_ev_ = nullptr;
-    int final_slot_ = -1;
     int result_ = WD_OK;
 };
 

@@ -29,12 +29,31 @@ namespace wd {
 Solve::Solve(wd_lattice *lat, const wd_solve_params &p, const double *b, double *x)
     : lat_(lat), p_(p), b_(b), x_(x), prec_(p.prec_inner) {}
 
+int SlotRes::create() {
+    if (hipHostMalloc((void **)&h_st, sizeof(RhsState) * kSlots * 12) != hipSuccess ||
+        hipHostMalloc((void **)&h_batch, sizeof(BatchState) * kSlots) != hipSuccess)
+        return fail(WD_ERR_NOMEM, "pinned host allocation failed");
+    for (int i = 0; i < kSlots; ++i)
+        if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess)
+            return fail(WD_ERR_HIP, "hipEventCreate failed");
+    if (hipEventCreateWithFlags(&final_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(WD_ERR_HIP, "hipEventCreate failed");
+    return WD_OK;
+}
+
+void SlotRes::destroy() {
+    for (int i = 0; i < kSlots; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (final_ev) (void)hipEventDestroy(final_ev);
+    if (h_st) (void)hipHostFree(h_st);
+    if (h_batch) (void)hipHostFree(h_batch);
+    *this = SlotRes{};
+}
+
 Solve::~Solve() {
-    for (auto e : events_) (void)hipEventDestroy(e);
-    if (final_ev_) (void)hipEventDestroy(final_ev_);
-    if (mem_) (void)hipFree(mem_);
-    if (h_st_) (void)hipHostFree(h_st_);
-    if (h_batch_) (void)hipHostFree(h_batch_);
+    // stream-ordered release after the solve's last kernel
+    if (mem_) (void)hipFreeAsync(mem_, s_);
+    own_.destroy();
 }
 
 int Solve::validate(wd_lattice *lat, const wd_solve_params *p) {
@@ -59,13 +78,12 @@ size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
     const int lo_xr = lo == WD_F16 ? WD_F32 : lo;
     size_t b = 6 * field_bytes(WD_F64, n);
     b += 2 * field_bytes(lo_xr, n) + 3 * field_bytes(lo, n);
-    const int bs = block_for_nrhs(p.nrhs);
-    b += align256((size_t)(blocks_for(n, bs) + 1) * p.nrhs * sizeof(double));
+    b += align256((size_t)reduce_partials_cap(lat->g, p.nrhs) * sizeof(double));
     b += align256(sizeof(RhsState) * 12) + 256;
     return b;
 }
 
-int Solve::setup(hipStream_t stream) {
+int Solve::setup(hipStream_t stream, SlotRes *res) {
     s_ = stream;
     const int V = lat_->g.V;
     const int nrhs = p_.nrhs;
@@ -80,10 +98,10 @@ int Solve::setup(hipStream_t stream) {
         gauge_lo_ = gauge64_;
     }
     bytes_ = footprint(lat_, p_);
-    hipError_t he = hipMalloc(&mem_, bytes_);
+    hipError_t he = hipMallocAsync(&mem_, bytes_, s_);
     if (he != hipSuccess) {
         mem_ = nullptr;
-        return fail(WD_ERR_NOMEM, "hipMalloc of %zu bytes of solver workspace failed: %s", bytes_,
+        return fail(WD_ERR_NOMEM, "allocation of %zu bytes of solver workspace failed: %s", bytes_,
                     hipGetErrorString(he));
     }
     char *base = (char *)mem_;
@@ -106,24 +124,24 @@ int Solve::setup(hipStream_t stream) {
     pl_ = next(prec_);
     tl_ = next(prec_);
     apl_ = next(prec_);
-    const int bs = block_for_nrhs(nrhs);
     partials_ = (double *)cur;
-    cur += align256((size_t)(blocks_for(n, bs) + 1) * nrhs * sizeof(double));
+    partials_cap_ = (int)reduce_partials_cap(lat_->g, nrhs);
+    cur += align256((size_t)partials_cap_ * sizeof(double));
     st_ = (RhsState *)cur;
     cur += align256(sizeof(RhsState) * 12);
     batch_ = (BatchState *)cur;
     cur += 256;
     if ((size_t)(cur - base) > bytes_) return fail(WD_ERR_STATE, "workspace layout overflow");
 
-    if (hipHostMalloc((void **)&h_st_, sizeof(RhsState) * kSlots * nrhs) != hipSuccess ||
-        hipHostMalloc((void **)&h_batch_, sizeof(BatchState) * kSlots) != hipSuccess)
-        return fail(WD_ERR_NOMEM, "pinned host allocation failed");
-    events_.resize(kSlots);
-    for (int i = 0; i < kSlots; ++i)
-        if (hipEventCreateWithFlags(&events_[i], hipEventDisableTiming) != hipSuccess)
-            return fail(WD_ERR_HIP, "hipEventCreate failed");
-    if (hipEventCreateWithFlags(&final_ev_, hipEventDisableTiming) != hipSuccess)
-        return fail(WD_ERR_HIP, "hipEventCreate failed");
+    if (!res) {
+        int rc = own_.create();
+        if (rc) return rc;
+        res = &own_;
+    }
+    res_ = res;
+    h_st_ = res->h_st;
+    h_batch_ = res->h_batch;
+    final_ev_ = res->final_ev;
 
     ctl_.tol2 = p_.tol * p_.tol;
     const double delta = p_.reliable_delta > 0 ? p_.reliable_delta : 0.1;
@@ -141,6 +159,7 @@ int Solve::setup(hipStream_t stream) {
 RedArgs Solve::red(int mode) const {
     RedArgs r{};
     r.partials = partials_;
+    r.partials_cap = partials_cap_;
     r.st = st_;
     r.batch = batch_;
     r.ctl = ctl_;
@@ -161,7 +180,7 @@ int Solve::start() {
         launch_zero(x64_, s_);
     launch_zero(xl_, s_);
     enqueue_reliable(true);
-    if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "kernel launch failed");
+    if (launch_failed()) return fail(WD_ERR_HIP, "kernel launch failed");
     return push_status();
 }
 
@@ -204,7 +223,6 @@ void Solve::enqueue_finish() {
     RedArgs rb = red(RED_AUX2);
     launch_norm(b64_, rb, s_);                  // |b|^2
     launch_export(x64_, x_, lat_->g, s_);
-    final_slot_ = 0;
     (void)hipMemcpyAsync(h_st_, st_, sizeof(RhsState) * p_.nrhs, hipMemcpyDeviceToHost, s_);
     (void)hipEventRecord(final_ev_, s_);
 }
@@ -218,9 +236,9 @@ int Solve::push_status() {
             hipSuccess ||
         hipMemcpyAsync(h_batch_ + slot, batch_, sizeof(BatchState), hipMemcpyDeviceToHost, s_) !=
             hipSuccess ||
-        hipEventRecord(events_[slot], s_) != hipSuccess)
+        hipEventRecord(res_->ev[slot], s_) != hipSuccess)
         return fail(WD_ERR_HIP, "status copy failed");
-    pending_.push_back(Pending{events_[slot], slot, epoch_});
+    pending_.push_back(Pending{res_->ev[slot], slot, epoch_});
     return WD_OK;
 }
 
@@ -246,7 +264,7 @@ int Solve::advance(bool block) {
         // keep two status reads in flight so the device never idles on the host
         while (pending_.size() < 2) {
             enqueue_inner(chunk_);
-            if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "kernel launch failed");
+            if (launch_failed()) return fail(WD_ERR_HIP, "kernel launch failed");
             int rc = push_status();
             if (rc) return rc;
         }
@@ -268,7 +286,7 @@ int Solve::advance(bool block) {
         }
         // every rhs converged or failed: pending inner chunks are no-ops
         enqueue_finish();
-        if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "kernel launch failed");
+        if (launch_failed()) return fail(WD_ERR_HIP, "kernel launch failed");
         phase_ = 1;
     }
 }
@@ -283,6 +301,7 @@ void Solve::info(wd_solve_info *out) const {
         o.true_rel_resid = st.rr0 > 0 ? std::sqrt(st.rr_true / st.rr0) : 0.0;
         o.rel_resid_D = st.aux2 > 0 ? std::sqrt(st.aux / st.aux2) : 0.0;
         o.seconds = seconds;
+        o.queued_seconds = 0.0;
     }
 }
 

@@ -206,7 +206,8 @@ enum RedMode {
 };
 
 struct RedArgs {
-    double *partials;    // >= nblocks * nrhs doubles (one per block and rhs)
+    double *partials;    // partials_cap doubles (one per block and rhs)
+    int partials_cap;    // launchers never use more blocks * nrhs than this
     RhsState *st;        // nrhs entries
     BatchState *batch;
     SolveCtl ctl;
@@ -225,6 +226,45 @@ inline int block_for_nrhs(int nrhs) {
 }
 
 inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// ------------------------------------------------------------------ launch shapes
+//
+// The time-marching stencil (one right-hand side) runs one workgroup of bvol
+// lanes per brick column and chunk of time slices; every other reducing
+// kernel runs blocks_for(V * nrhs, block_for_nrhs(nrhs)) workgroups.  The
+// solver sizes its reduction partials from these same functions.
+
+inline bool tm_eligible(const Geom &g, int nrhs) {
+    return nrhs == 1 && g.bvol % 64 == 0 && g.bvol <= 256;
+}
+
+// time slices per chunk: enough workgroups to fill the chip (a multiple of
+// 8 chunks where the extent allows); env_chunk > 0 overrides (tuning)
+inline int tm_chunk_len(const Geom &g, int env_chunk) {
+    const int Lt = g.L[3];
+    if (env_chunk > 0) return env_chunk < Lt ? env_chunk : Lt;
+    const int ncols = g.V / (Lt * g.bvol);
+    int nch = 8;
+    while (nch < Lt && ncols * nch < 2048) nch += 8;
+    if (nch > Lt) nch = Lt;
+    return (Lt + nch - 1) / nch;
+}
+
+inline int tm_blocks(const Geom &g, int chunk_len) {
+    const int ncols = g.V / (g.L[3] * g.bvol);
+    return ncols * ((g.L[3] + chunk_len - 1) / chunk_len);
+}
+
+// partial sums any reducing launch on this geometry may write (the time
+// marching stencil uses at most V / 64 blocks whatever its chunk length)
+inline int64_t reduce_partials_cap(const Geom &g, int nrhs) {
+    int64_t nb = blocks_for((int64_t)g.V * nrhs, block_for_nrhs(nrhs));
+    if (tm_eligible(g, nrhs)) {
+        const int64_t tmb = (int64_t)g.V / 64;
+        if (tmb > nb) nb = tmb;
+    }
+    return (nb + 1) * nrhs;
+}
 
 // ------------------------------------------------------------------ launchers
 // (defined in the .hip files; all stream-ordered, no host synchronisation)

@@ -40,6 +40,15 @@ static int check(int Lx, int Ly, int Lz, int Lt) {
             }
             for (int s = 0; s < g.V; ++s)
                 if (seen[s] != 1) ++fails;
+            // reduction partials: room for every reducing launch shape
+            for (int nrhs = 1; nrhs <= 12; ++nrhs) {
+                const long long cap = wd::reduce_partials_cap(g, nrhs);
+                const int bs = wd::block_for_nrhs(nrhs);
+                if ((long long)wd::blocks_for((long long)g.V * nrhs, bs) * nrhs > cap) ++fails;
+                if (wd::tm_eligible(g, nrhs))
+                    for (int ch = 1; ch <= Lt; ++ch)
+                        if (wd::tm_blocks(g, ch) > cap) ++fails;
+            }
         }
       }
     }
@@ -57,6 +66,8 @@ int main() {
     f += check(6, 4, 12, 2);
     f += check(48, 12, 4, 2);
     f += check(24, 6, 8, 4);
+    f += check(12, 12, 12, 12);
+    f += check(16, 16, 16, 8);
     printf(f ? "FAIL\n" : "OK\n");
     return f ? 1 : 0;
 }
