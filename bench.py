@@ -6,15 +6,23 @@ One step = gauge ingest (canonical -> packed forms) + the plain FP64 CG solve
 + the mixed-precision solve (FP16-12 inner, FP64 reliable updates) of the
 same source, every kernel in libwdirac.  `value` is the whole-step stencil
 throughput: stencil applications x V x 1320 flop over the step wall time.
-The JSON line also carries the time to solution of each solver, the stencil
-kernel roofline (HIP events on the launch stream) and the CPU oracle's
+The JSON line also carries the time to solution of each solver, the FP64
+stencil's roofline (HIP events recorded on its launch stream, traffic from
+the committed counter summary when it matches the current kernel source),
+the stencil alone per precision, the 12-source batched solve on 24^3 x 48,
+a Poisson request stream through the solve server, and the CPU oracle's
 stencil throughput.  Inputs are synthetic and resident in HBM before timing.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--small] [--no-extras]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+    python bench.py --probe                  # workload for rocprofv3 counter runs
+    python bench.py --pmc-summary FETCH.csv WRITE.csv --out profiles/X.json --cmd "..."
+    python bench.py --trace-summary STATS.csv --out profiles/X.md --cmd "..."
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import statistics
@@ -28,8 +36,12 @@ FLOP_PER_SITE = 1320
 # algorithmic bytes per site of one stencil application: spinor in once,
 # four links per site (each read once), spinor out once
 BYTES_PER_SITE = {"f64": 192 + 576 + 192, "f32": 96 + 192 + 96, "f16": 52 + 96 + 52}
+LINK_BYTES = {"f64": 576, "f32": 192, "f16": 96}
+SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52}
 HBM_PEAK_GBS = 8000.0
 METRIC = "dslash GFLOP/s & HBM GB/s; CG time-to-1e-10 residual, mixed vs FP64"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_traffic_48x48x48x96.json")
+KERNEL_SOURCES = ["dslash.hip", "device.hpp", "wd_internal.hpp"]
 
 
 def log(*a):
@@ -45,10 +57,23 @@ def parse():
     ap.add_argument("--kappa", type=float, default=0.1245)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--mixed", default="f16", choices=["f32", "f16"])
-    ap.add_argument("--small", action="store_true", help="16^3x32 quick run")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--trace-summary", metavar="STATS_CSV")
+    ap.add_argument("--out")
+    ap.add_argument("--cmd", default="")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_04201_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def applications(info, prec_inner):
@@ -62,8 +87,28 @@ def applications(info, prec_inner):
     return {"f64": f64, prec_inner: inner}
 
 
+def load_traffic(prec):
+    """HBM traffic per launch from the committed counter summary, or None if
+    it is missing or was taken on a different stencil source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(f"dslash_{prec}")
+    return None if k is None else k.get("traffic_bytes")
+
+
+# ------------------------------------------------------------------ main bench
+
 def main():
     args = parse()
+    if args.pmc_summary:
+        return pmc_summary(args)
+    if args.trace_summary:
+        return trace_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                           "(the multi-GPU halo-exchange path is a design, not built)"}))
@@ -74,7 +119,10 @@ def main():
     import synth
     import paper_1810_04201_amd as wd
 
-    dims = (16, 16, 16, 32) if args.small else tuple(int(v) for v in args.dims.split("x"))
+    if args.probe:
+        return probe(np, torch, synth, wd)
+
+    dims = tuple(int(v) for v in args.dims.split("x"))
     V = int(np.prod(dims))
     kappa = args.kappa
     dev = torch.device("cuda:0")
@@ -99,12 +147,10 @@ def main():
             xd.zero_()
             xm.zero_()
             rc1, i1 = lat.solve(bd, xd, kappa, tol=args.tol, prec="f64", stream=stream)
-            ta = time.time()
             rc2, i2 = lat.solve(bd, xm, kappa, tol=args.tol, prec=args.mixed, stream=stream)
-            tb = time.time()
         if rc1 != 0 or rc2 != 0:
             raise RuntimeError(f"solve failed: {rc1} {i1} {rc2} {i2}")
-        return i1[0], i2[0], tb - ta
+        return i1[0], i2[0]
 
     for w in range(args.warmup):
         step()
@@ -117,7 +163,7 @@ def main():
     per_step = []
     for k in range(args.steps):
         ts = time.time()
-        i1, i2, tmix = step()
+        i1, i2 = step()
         torch.cuda.synchronize()
         per_step.append({"t": time.time() - ts, "fp64": i1, "mixed": i2})
         for info, p in ((i1, "f64"), (i2, args.mixed)):
@@ -128,7 +174,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.time() - t_start
     wd.wd_timing_enable(False)
-    ms64, cnt64 = wd.wd_timing_read("dslash_f64")
+    ms64, _ = wd.wd_timing_read("dslash_f64")
     msl, cntl = wd.wd_timing_read("dslash_" + args.mixed)
 
     total_apps = sum(apps.values())
@@ -139,6 +185,7 @@ def main():
     t_fp64 = statistics.median(s["fp64"]["seconds"] for s in per_step)
     t_mix = statistics.median(s["mixed"]["seconds"] for s in per_step)
     s0 = per_step[-1]
+    traffic = load_traffic("f64") if dims == (48, 48, 48, 96) else None
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -172,13 +219,15 @@ def main():
             "speedup_mixed_vs_fp64": round(t_fp64 / t_mix, 3),
         },
         "roofline": {
-            "kernel": "dslash_f64 (k_dslash<F64>)",
+            "kernel": "dslash_f64 (k_dslash_tm<F64>, time-marching stencil)",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": (round(traffic / (avg64_ms * 1e-3) / 1e9, 1) if traffic else None),
+            "traffic_bytes_per_launch": traffic,
+            "algorithmic_bytes_per_launch": V * BYTES_PER_SITE["f64"],
             "avg_launch_ms": round(avg64_ms, 4),
             "launches": apps["f64"],
             "bytes_per_site": BYTES_PER_SITE["f64"],
@@ -186,22 +235,31 @@ def main():
         },
     }
     if cntl:
+        ml = msl / apps[args.mixed]
         out["roofline_" + args.mixed] = {
-            "avg_launch_ms": round(msl / apps[args.mixed], 4),
-            "achieved_GBps": round(V * BYTES_PER_SITE[args.mixed] /
-                                   (msl / apps[args.mixed] * 1e-3) / 1e9, 1),
-            "GFLOPs": round(V * FLOP_PER_SITE / (msl / apps[args.mixed] * 1e-3) / 1e9, 1),
+            "avg_launch_ms": round(ml, 4),
+            "achieved_GBps": round(V * BYTES_PER_SITE[args.mixed] / (ml * 1e-3) / 1e9, 1),
+            "GFLOPs": round(V * FLOP_PER_SITE / (ml * 1e-3) / 1e9, 1),
         }
     if not args.no_extras:
-        out["extras"] = extras(args, wd, torch, np, lat, Ud, bd, dims, V, kappa, stream)
+        ex = {}
+        ex.update(stencil_alone(wd, torch, lat, bd, V, kappa, stream))
+        ex.update(other_mixed(args, lat, bd, kappa, stream, torch))
+        lat.close()
+        del Ud
+        torch.cuda.empty_cache()
+        ex["multi_rhs"] = multi_rhs(np, torch, synth, wd)
+        ex["serving"] = serving(np, torch, synth, wd, args.serve_requests)
+        out["extras"] = ex
+    else:
+        lat.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(np)
-    lat.close()
     print(json.dumps(out))
 
 
-def extras(args, wd, torch, np, lat, Ud, bd, dims, V, kappa, stream):
-    """Stencil kernel alone per precision and the other mixed variant."""
+def stencil_alone(wd, torch, lat, bd, V, kappa, stream):
+    """The stencil alone on resident fields, per precision (HIP events)."""
     res = {}
     for prec in ("f64", "f32", "f16"):
         fa = wd.Field(lat, prec)
@@ -224,14 +282,143 @@ def extras(args, wd, torch, np, lat, Ud, bd, dims, V, kappa, stream):
                                  "GBps_algorithmic": round(V * BYTES_PER_SITE[prec] / ms / 1e6, 1)}
         fa.close()
         fb.close()
+    log(f"stencil alone: {res}")
+    return res
+
+
+def other_mixed(args, lat, bd, kappa, stream, torch):
     other = "f32" if args.mixed == "f16" else "f16"
     xo = torch.zeros_like(bd)
     with torch.cuda.stream(stream):
         rc, info = lat.solve(bd, xo, kappa, tol=args.tol, prec=other, stream=stream)
-    res[f"mixed_{other}_s"] = round(info[0]["seconds"], 3)
-    res[f"mixed_{other}_iters"] = info[0]["iters"]
-    res[f"mixed_{other}_true_rel_resid"] = info[0]["true_rel_resid"]
-    log(f"extras: {res}")
+    return {f"mixed_{other}_s": round(info[0]["seconds"], 3),
+            f"mixed_{other}_iters": info[0]["iters"],
+            f"mixed_{other}_true_rel_resid": info[0]["true_rel_resid"]}
+
+
+def multi_rhs(np, torch, synth, wd):
+    """24^3 x 48, kappa 0.124, eps = 0.3 links seed 4: the 12 spin-colour point
+    sources at the origin solved in one batched call (FP32-12 inner, FP64
+    reliable updates) versus 12 single solves; and the batched stencil."""
+    dims = (24, 24, 24, 48)
+    V = int(np.prod(dims))
+    dev = torch.device("cuda:0")
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.gauge(dims, 4, synth.EXP, 0.3)).to(dev))
+    B = torch.from_numpy(synth.spin_colour_point_sources(dims)).to(dev)
+    X = torch.zeros_like(B)
+    lat.solve(B, X, 0.124, tol=1e-10, prec="f32", nrhs=12)  # warm
+    torch.cuda.synchronize()
+    t = time.time()
+    rc, info = lat.solve(B, X, 0.124, tol=1e-10, prec="f32", nrhs=12)
+    torch.cuda.synchronize()
+    t12 = time.time() - t
+    x1 = torch.zeros_like(B[0])
+    t = time.time()
+    single = []
+    for k in range(12):
+        r1, i1 = lat.solve(B[k].contiguous(), x1, 0.124, tol=1e-10, prec="f32")
+        single.append(i1[0])
+    torch.cuda.synchronize()
+    t1 = time.time() - t
+    # batched stencil versus one source, FP32-12
+    res = {"lattice": "24x24x24x48", "rhs": 12, "batched_s": round(t12, 3),
+           "sequential_12_s": round(t1, 3), "speedup": round(t1 / t12, 3),
+           "max_iters": max(i["iters"] for i in info),
+           "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}
+    for nrhs in (1, 12):
+        fa = wd.Field(lat, "f32", nrhs=nrhs)
+        fb = wd.Field(lat, "f32", nrhs=nrhs)
+        fa.load(B[:nrhs].contiguous() if nrhs > 1 else B[0].contiguous())
+        for _ in range(3):
+            wd.wd_dslash(lat, 0.124, 0, fa, fb)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            wd.wd_dslash(lat, 0.124, 0, fa, fb)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        alg = V * (LINK_BYTES["f32"] + nrhs * 2 * SPINOR_BYTES["f32"])
+        res[f"dslash_f32_nrhs{nrhs}_ms"] = round(ms, 4)
+        res[f"dslash_f32_nrhs{nrhs}_bytes_per_rhs_site"] = round(alg / (V * nrhs), 1)
+        res[f"dslash_f32_nrhs{nrhs}_GBps_algorithmic"] = round(alg / ms / 1e6, 1)
+        res[f"dslash_f32_nrhs{nrhs}_GFLOPs"] = round(V * nrhs * FLOP_PER_SITE / ms / 1e6, 1)
+        fa.close()
+        fb.close()
+    lat.close()
+    log(f"multi-rhs: {res}")
+    return res
+
+
+def serving(np, torch, synth, wd, n_requests):
+    """Poisson request stream through the solve server: lattices uniform over
+    {8^4, 12^4, 16^3x32, 24^3x48} (two eps = 0.3 gauge fields each), kappa
+    uniform in [0.115, 0.1245], 1-12 sources, tol 1e-10, mixed FP32-12;
+    64 GiB budget.  The arrival rate is 0.7 x the closed-loop rate measured
+    first with 16 requests submitted at once."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    sizes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (24, 24, 24, 48)]
+    lats, srcs = [], {}
+    for d in sizes:
+        for seed in (61, 62):
+            lat = wd.Lattice(d)
+            lat.set_gauge(torch.from_numpy(synth.gauge(d, seed + 10 * len(lats), synth.EXP, 0.3)).to(dev))
+            lats.append(lat)
+        srcs[d] = torch.from_numpy(synth.gaussian_sources(d, [500 + k for k in range(12)])).to(dev)
+
+    def draw():
+        lat = lats[rng.integers(len(lats))]
+        return lat, float(rng.uniform(0.115, 0.1245)), int(rng.integers(1, 13))
+
+    def run(srv, reqs, arrivals):
+        live, done = {}, {}
+        t0 = time.time()
+        k = 0
+        while len(done) < len(reqs):
+            now = time.time() - t0
+            while k < len(reqs) and arrivals[k] <= now:
+                lat, kap, nrhs = reqs[k]
+                b = srcs[lat.dims][:nrhs]
+                b = b[0] if nrhs == 1 else b
+                x = torch.empty_like(b)
+                live[srv.submit(lat, b, x, kap, tol=1e-10, prec="f32", nrhs=nrhs)] = (b, x)
+                k += 1
+            for t in list(live):
+                rc, info = srv.poll(t)
+                if rc != wd.WD_PENDING:
+                    done[t] = (rc, info)
+                    del live[t]
+            time.sleep(0.0005)
+        return done
+
+    budget = 64 << 30
+    srv = wd.Server(budget, max_active=8)
+    closed = [draw() for _ in range(16)]
+    t = time.time()
+    d0 = run(srv, closed, [0.0] * 16)
+    rate = 16 / (time.time() - t)
+    srv.close()
+    lam = 0.7 * rate
+    reqs = [draw() for _ in range(n_requests)]
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
+    srv = wd.Server(budget, max_active=8)
+    d1 = run(srv, reqs, arrivals)
+    st = srv.stats()
+    peak = srv.peak_bytes()
+    srv.close()
+    ok = sum(1 for rc, _ in d1.values() if rc == 0)
+    worst = max(max(i["true_rel_resid"] for i in info) for rc, info in d1.values())
+    for lat in lats:
+        lat.close()
+    res = {"requests": n_requests, "closed_loop_solves_per_s": round(rate, 2),
+           "arrival_rate_per_s": round(lam, 2), "solves_per_s": round(st["solves_per_s"], 2),
+           "p50_latency_s": round(st["p50_s"], 4), "p99_latency_s": round(st["p99_s"], 4),
+           "succeeded": ok, "max_true_rel_resid": worst, "peak_bytes": peak,
+           "budget_bytes": budget, "closed_loop_ok": sum(1 for rc, _ in d0.values() if rc == 0)}
+    log(f"serving: {res}")
     return res
 
 
@@ -249,16 +436,126 @@ def cpu_baseline(np):
         wilson.apply_D(U, psi, dims, 0.124)
         ts.append(time.time() - t)
     t = statistics.median(ts)
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        blas = 1
     return {"value": round(V * FLOP_PER_SITE / t / 1e9, 3), "unit": "GFLOP/s",
             "cores": 1, "kind": "oracle",
             "sample": f"oracle apply_D (NumPy einsum stencil, complex128) on 16^3x32, median of 3 "
                       f"runs of {t:.2f}s; 1 thread used (einsum is single-threaded), "
-                      f"{os.cpu_count()} cores present, BLAS pool {blas} unused"}
+                      f"{os.cpu_count()} cores present"}
+
+
+# ------------------------------------------------------------------ profiling helpers
+
+def probe(np, torch, synth, wd):
+    """Workload for counter runs: a plain 2 GiB copy (calibration), then three
+    stencil sweeps per precision at 48^3 x 96."""
+    dev = torch.device("cuda:0")
+    n = 256 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    dims = (48, 48, 48, 96)
+    V = int(np.prod(dims))
+    U = torch.empty((V, 4, 3, 3, 2), dtype=torch.float64, pin_memory=True)
+    synth.gauge(dims, 3, synth.EXP, 0.3, out=U.numpy())
+    lat = wd.Lattice(dims)
+    Ud = U.to(dev)
+    lat.set_gauge(Ud)
+    del Ud
+    psi = torch.from_numpy(synth.gaussian_spinor(dims, 103)).to(dev)
+    for prec in ("f64", "f32", "f16"):
+        fa = wd.Field(lat, prec)
+        fb = wd.Field(lat, prec)
+        fa.load(psi)
+        for _ in range(3):
+            wd.wd_dslash(lat, 0.1245, 0, fa, fb)
+        torch.cuda.synchronize()
+        fa.close()
+        fb.close()
+        print(f"probe {prec} done", flush=True)
+    lat.close()
+
+
+def _pmc_rows(path):
+    rows = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            key = int(r["Dispatch_Id"])
+            e = rows.setdefault(key, {"name": r["Kernel_Name"], "grid": int(r["Grid_Size"])})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+    return [rows[k] for k in sorted(rows)]
+
+
+def pmc_summary(args):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the probe, scaled by
+    what the same counters read for the plain copy of known size."""
+    fetch = _pmc_rows(args.pmc_summary[0])
+    write = _pmc_rows(args.pmc_summary[1])
+    copy_bytes = 256 * 1024 * 1024 * 8
+    cf = [r for r in fetch if "copyBuffer" in r["name"]]
+    cw = [r for r in write if "copyBuffer" in r["name"]]
+    ff = copy_bytes / (statistics.median(r["FETCH_SIZE"] for r in cf) * 1024)
+    wf = copy_bytes / (statistics.median(r["WRITE_SIZE"] for r in cw) * 1024)
+    V = 48 * 48 * 48 * 96
+    out = {"command": args.cmd, "source_sha256": kernel_source_hash(),
+           "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
+                                "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+           "kernels": {}}
+    for prec, tag in (("f64", "k_dslash_tm<0"), ("f32", "k_dslash_tm<1"), ("f16", "k_dslash_tm<2")):
+        fr = [r for r in fetch if tag in r["name"]]
+        wr = [r for r in write if tag in r["name"]]
+        if not fr or not wr:
+            continue
+        big = max(r["grid"] for r in fr)
+        fk = statistics.median(r["FETCH_SIZE"] for r in fr if r["grid"] == big)
+        wk = statistics.median(r["WRITE_SIZE"] for r in wr if r["grid"] == big)
+        traffic = fk * 1024 * ff + wk * 1024 * wf
+        alg = V * BYTES_PER_SITE[prec]
+        out["kernels"][f"dslash_{prec}"] = {
+            "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk, "traffic_bytes": round(traffic),
+            "algorithmic_bytes": alg, "traffic_over_algorithmic": round(traffic / alg, 3),
+            "traffic_bytes_per_site": round(traffic / V, 1)}
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
+def trace_summary(args):
+    """Short markdown table of a rocprofv3 --stats kernel summary.  With the
+    sibling *_kernel_trace.csv it also averages only the launches that did
+    work (over 1% of the kernel's longest): iterations enqueued after a solve
+    converged return at once and would dilute the plain average."""
+    with open(args.trace_summary) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+    busy = {}
+    tr = args.trace_summary.replace("_kernel_stats.csv", "_kernel_trace.csv")
+    if os.path.exists(tr):
+        durs = {}
+        with open(tr) as f:
+            for r in csv.DictReader(f):
+                d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                durs.setdefault(r["Kernel_Name"], []).append(d)
+        for name, ds in durs.items():
+            m = max(ds)
+            real = [d for d in ds if d > 0.01 * m]
+            busy[name] = (len(real), sum(real) / len(real) / 1e6)
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{args.cmd}`", "",
+             "| kernel | calls | total ms | avg ms | working launches | avg ms (working) | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows[:20]:
+        name = r["Name"].replace("|", "/")
+        n, a = busy.get(r["Name"], ("", None))
+        short = name if len(name) <= 90 else name[:87] + "..."
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e6:.4f} | {n} | "
+                     f"{'' if a is None else f'{a:.4f}'} | {float(r['Percentage']):.1f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 if __name__ == "__main__":
