@@ -113,17 +113,18 @@ int wd_apply_D(wd_lattice *lat, double kappa, int prec, const double *in, double
 int wd_apply_Ddag(wd_lattice *lat, double kappa, int prec, const double *in, double *out,
                   void *stream);
 
-/* Batched form: nrhs (1..12) canonical spinors stacked as [rhs][V][24]; each
- * gauge link is loaded once per site for all right-hand sides. */
+/* Batched form: nrhs (1..12) canonical spinors stacked as [rhs][V][24].  The
+ * workgroups of all right-hand sides on the same sites run side by side, so
+ * a gauge link is read from HBM about once per site for all of them. */
 int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, const double *in,
              double *out, void *stream);
 
 /* --------------------------------------------------- fields (internal layout)
  * A wd_field holds nrhs spinors in the layout the kernels use: sites in
  * brick-column order (bricks of the lattice, each column marching in t),
- * entries site * nrhs + rhs grouped in tiles of 64, and inside a tile one
- * contiguous run per spin-colour component (plus per-entry float32 scales
- * for WD_F16).  The layout is private; import/export convert from/to the
+ * one right-hand side after another (each padded to whole tiles of 64
+ * sites), and inside a tile one contiguous run per spin-colour component
+ * (plus per-site float32 scales for WD_F16).  The layout is private; import/export convert from/to the
  * canonical order.  Fields time the stencil on resident data and chain
  * operators without the canonical round trip. */
 int wd_field_create(wd_lattice *lat, int prec, int nrhs, wd_field **out);

@@ -8,34 +8,45 @@
 
 namespace wd {
 
-static constexpr int kBS = 256;
+static constexpr int kBS = 256;  // gauge kernels (one lane per site)
 
 // ------------------------------------------------------------------ reduction phase 2
 
 // One block: fixed-order sum of nb partials per rhs, then the finaliser.
+// The order for an rhs does not depend on nrhs (thread t sums partials
+// t, t + 256, ...; a butterfly inside each wave; the four waves in order),
+// so a batched solve reproduces the single-rhs solves bit for bit.
 // gated: skip when no rhs is iterating (the producing kernel returned early
 // and wrote no partials).
 constexpr int kFinalizeThreads = 256;
 
 __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(RedArgs red, int nb, int gated) {
     if (gated && red.batch->n_active == 0) return;
-    __shared__ double sm[kFinalizeThreads];
+    __shared__ double sm[(kFinalizeThreads / 64) * 12];
     const int nrhs = red.ctl.nrhs;
-    const int tid = threadIdx.x;
-    int S = kFinalizeThreads;
-    while (S * nrhs > kFinalizeThreads) S >>= 1;
-    const int slot = tid / nrhs;
-    const int r = tid - slot * nrhs;
-    double acc = 0.0;
-    if (slot < S)
-        for (int b = slot; b < nb; b += S) acc += red.partials[(size_t)b * nrhs + r];
-    sm[tid] = acc;
-    __syncthreads();
-    for (int stride = S >> 1; stride > 0; stride >>= 1) {
-        if (tid < stride * nrhs) sm[tid] += sm[tid + stride * nrhs];
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double acc[12];
+#pragma unroll
+    for (int r = 0; r < 12; ++r) acc[r] = 0.0;
+    for (int b = tid; b < nb; b += kFinalizeThreads) {
+        const double *p = red.partials + (size_t)b * nrhs;
+#pragma unroll
+        for (int r = 0; r < 12; ++r)
+            if (r < nrhs) acc[r] += p[r];
     }
-    if (tid < nrhs && red.mode != RED_NONE) finalize_rhs(red, tid, sm[tid]);
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+        double v = acc[r];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sm[w * 12 + r] = v;
+    }
+    __syncthreads();
+    if (tid < nrhs && red.mode != RED_NONE) {
+        double t = 0.0;
+        for (int k = 0; k < kFinalizeThreads / 64; ++k) t += sm[k * 12 + tid];
+        finalize_rhs(red, tid, t);
+    }
     __syncthreads();
     if (tid == 0 && red.mode != RED_NONE) recount_batch(red);
 }
@@ -109,12 +120,17 @@ __device__ __forceinline__ void store_from_double(const FieldRef &f, int i, cons
     Spinor<PREC>::store(f, i, t);
 }
 
-// canonical [rhs][s][12][re,im] (lexicographic s) -> field entry i*nrhs + rhs
+// Every field kernel below runs a grid of site_blocks(V) x nrhs workgroups:
+// lane = site of the rhs blockIdx.y, so gating by the solver state is
+// uniform over a workgroup.
+static dim3 field_grid(const FieldRef &f) { return dim3(site_blocks(f.V), f.nrhs); }
+
+// canonical [rhs][s][12][re,im] (lexicographic s) -> internal site i of rhs
 template <int PREC>
 __global__ void k_import(const double2 *__restrict__ canon, FieldRef f, Geom geo) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= f.n) return;
-    const int i = e / f.nrhs, r = e - i * f.nrhs;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= geo.V) return;
+    const int r = blockIdx.y;
     int x, y, z, t;
     coords_of(geo, i, x, y, z, t);
     const double2 *src = canon + ((size_t)r * geo.V + lex_of(geo, x, y, z, t)) * 12;
@@ -124,18 +140,18 @@ __global__ void k_import(const double2 *__restrict__ canon, FieldRef f, Geom geo
         double2 d = src[k];
         v[k] = {d.x, d.y};
     }
-    store_from_double<PREC>(f, e, v);
+    store_from_double<PREC>(rhs_view(f, r), i, v);
 }
 
 template <int PREC>
 __global__ void k_export(FieldRef f, double2 *__restrict__ canon, Geom geo) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= f.n) return;
-    const int i = e / f.nrhs, r = e - i * f.nrhs;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= geo.V) return;
+    const int r = blockIdx.y;
     int x, y, z, t;
     coords_of(geo, i, x, y, z, t);
     cx<double> v[12];
-    load_as_double<PREC>(f, e, v);
+    load_as_double<PREC>(rhs_view(f, r), i, v);
     double2 *dst = canon + ((size_t)r * geo.V + lex_of(geo, x, y, z, t)) * 12;
 #pragma unroll
     for (int k = 0; k < 12; ++k) dst[k] = make_double2(v[k].re, v[k].im);
@@ -144,40 +160,43 @@ __global__ void k_export(FieldRef f, double2 *__restrict__ canon, Geom geo) {
 template <int SRC, int DST>
 __global__ void k_convert(FieldRef a, FieldRef b, Gate gate) {
     if (gate.batch && gate.batch->n_active == 0) return;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.n) return;
-    if (gate.st && !gate.st[e % a.nrhs].active) return;
+    const int r = blockIdx.y;
+    if (gate.st && !gate.st[r].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.V) return;
     cx<double> v[12];
-    load_as_double<SRC>(a, e, v);
-    store_from_double<DST>(b, e, v);
+    load_as_double<SRC>(rhs_view(a, r), i, v);
+    store_from_double<DST>(rhs_view(b, r), i, v);
 }
 
 template <int PREC>
 __global__ void k_zero(FieldRef f) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= f.n) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= f.V) return;
     cx<double> v[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = {0.0, 0.0};
-    store_from_double<PREC>(f, e, v);
+    store_from_double<PREC>(rhs_view(f, blockIdx.y), i, v);
 }
 
 // x64 += xlo ; xlo = 0 for rhs not yet converged
 template <int PL>
 __global__ void k_accum_zero(FieldRef x, FieldRef xl, const RhsState *st) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= x.n) return;
-    if (st[e % x.nrhs].converged) return;
+    const int r = blockIdx.y;
+    if (st[r].converged) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= x.V) return;
+    const FieldRef xv = rhs_view(x, r), lv = rhs_view(xl, r);
     cx<double> a[12], b[12], z[12];
-    load_as_double<WD_F64>(x, e, a);
-    load_as_double<PL>(xl, e, b);
+    load_as_double<WD_F64>(xv, i, a);
+    load_as_double<PL>(lv, i, b);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         a[k] = a[k] + b[k];
         z[k] = {0.0, 0.0};
     }
-    store_from_double<WD_F64>(x, e, a);
-    store_from_double<PL>(xl, e, z);
+    store_from_double<WD_F64>(xv, i, a);
+    store_from_double<PL>(lv, i, z);
 }
 
 #define WD_DISPATCH_PREC(P, ...)                   \
@@ -188,22 +207,22 @@ __global__ void k_accum_zero(FieldRef x, FieldRef xl, const RhsState *st) {
     }
 
 void launch_import(const double *canon, FieldRef f, const Geom &geo, hipStream_t s) {
-    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_import<PP>, dim3(blocks_for(f.n, kBS)),
-                                                dim3(kBS), 0, s, (const double2 *)canon, f, geo));
+    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_import<PP>, field_grid(f), dim3(kSiteBlock), 0,
+                                                s, (const double2 *)canon, f, geo));
 }
 
 void launch_export(FieldRef f, double *canon, const Geom &geo, hipStream_t s) {
-    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_export<PP>, dim3(blocks_for(f.n, kBS)),
-                                                dim3(kBS), 0, s, f, (double2 *)canon, geo));
+    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_export<PP>, field_grid(f), dim3(kSiteBlock), 0,
+                                                s, f, (double2 *)canon, geo));
 }
 
 template <int SRC>
 static void convert_to(FieldRef a, FieldRef b, Gate gate, hipStream_t s) {
-    const int nb = blocks_for(a.n, kBS);
+    const dim3 gr = field_grid(a), bs(kSiteBlock);
     switch (b.prec) {
-        case WD_F64: hipLaunchKernelGGL((k_convert<SRC, WD_F64>), dim3(nb), dim3(kBS), 0, s, a, b, gate); break;
-        case WD_F32: hipLaunchKernelGGL((k_convert<SRC, WD_F32>), dim3(nb), dim3(kBS), 0, s, a, b, gate); break;
-        default: hipLaunchKernelGGL((k_convert<SRC, WD_F16>), dim3(nb), dim3(kBS), 0, s, a, b, gate); break;
+        case WD_F64: hipLaunchKernelGGL((k_convert<SRC, WD_F64>), gr, bs, 0, s, a, b, gate); break;
+        case WD_F32: hipLaunchKernelGGL((k_convert<SRC, WD_F32>), gr, bs, 0, s, a, b, gate); break;
+        default: hipLaunchKernelGGL((k_convert<SRC, WD_F16>), gr, bs, 0, s, a, b, gate); break;
     }
 }
 
@@ -213,65 +232,69 @@ void launch_convert(FieldRef a, FieldRef b, Gate gate, hipStream_t s) {
 
 void launch_zero(FieldRef f, hipStream_t s) {
     WD_DISPATCH_PREC(f.prec,
-                     hipLaunchKernelGGL(k_zero<PP>, dim3(blocks_for(f.n, kBS)), dim3(kBS), 0, s, f));
+                     hipLaunchKernelGGL(k_zero<PP>, field_grid(f), dim3(kSiteBlock), 0, s, f));
 }
 
 void launch_accum_zero(FieldRef x, FieldRef xl, const RhsState *st, hipStream_t s) {
-    WD_DISPATCH_PREC(xl.prec, hipLaunchKernelGGL(k_accum_zero<PP>, dim3(blocks_for(x.n, kBS)),
-                                                 dim3(kBS), 0, s, x, xl, st));
+    WD_DISPATCH_PREC(xl.prec, hipLaunchKernelGGL(k_accum_zero<PP>, field_grid(x),
+                                                 dim3(kSiteBlock), 0, s, x, xl, st));
 }
 
 // ------------------------------------------------------------------ CG updates
 
 // x += alpha p ; r -= alpha Ap ; |r|^2.  x, r in precision PX (F64 or F32);
 // p, Ap in PP (same as PX, or F16 with PX = F32).  Arithmetic in the compute
-// type of PX, the norm in float64.
+// type of PX, the norm in float64.  A frozen rhs's workgroups return at once
+// (the finaliser ignores its partials).
 template <int PX, int PPP>
 __global__ void k_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, RedArgs red,
                             Gate gate) {
     if (gate.batch->n_active == 0) return;
+    const int rhs = blockIdx.y;
+    if (!gate.st[rhs].active) return;
     using R = typename Spinor<PX>::R;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nrhs = x.nrhs;
-    const int rhs = e % nrhs;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double nrm = 0.0;
-    if (e < x.n && gate.st[rhs].active) {
+    if (i < x.V) {
+        const FieldRef xf = rhs_view(x, rhs), rf = rhs_view(r, rhs);
         const R alpha = (R)gate.st[rhs].alpha;
         cx<R> xv[12], rv[12], pv[12], av[12];
-        Spinor<PX>::load(x, e, xv);
-        Spinor<PX>::load(r, e, rv);
-        Spinor<PPP>::load(p, e, pv);
-        Spinor<PPP>::load(Ap, e, av);
+        Spinor<PX>::load(xf, i, xv);
+        Spinor<PX>::load(rf, i, rv);
+        Spinor<PPP>::load(rhs_view(p, rhs), i, pv);
+        Spinor<PPP>::load(rhs_view(Ap, rhs), i, av);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             xv[k] = {xv[k].re + alpha * pv[k].re, xv[k].im + alpha * pv[k].im};
             rv[k] = {rv[k].re - alpha * av[k].re, rv[k].im - alpha * av[k].im};
             nrm += (double)rv[k].re * (double)rv[k].re + (double)rv[k].im * (double)rv[k].im;
         }
-        Spinor<PX>::store(x, e, xv);
-        Spinor<PX>::store(r, e, rv);
+        Spinor<PX>::store(xf, i, xv);
+        Spinor<PX>::store(rf, i, rv);
     }
-    reduce_block(nrm, red.partials, nrhs);
+    reduce_block(nrm, red.partials, (size_t)blockIdx.x * x.nrhs + rhs);
 }
 
 // p = r + beta p (RESTART: at the first reliable update p = r)
 template <int PX, int PPP, bool RESTART>
 __global__ void k_update_p(FieldRef p, FieldRef r, Gate gate) {
     if (gate.batch->n_active == 0) return;
-    using R = typename Spinor<PX>::R;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= p.n) return;
-    const RhsState &st = gate.st[e % p.nrhs];
+    const int rhs = blockIdx.y;
+    const RhsState &st = gate.st[rhs];
     if (!st.active) return;
+    using R = typename Spinor<PX>::R;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.V) return;
+    const FieldRef pf = rhs_view(p, rhs);
     cx<R> rv[12], pv[12];
-    Spinor<PX>::load(r, e, rv);
+    Spinor<PX>::load(rhs_view(r, rhs), i, rv);
     if (RESTART && st.updates == 1) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) pv[k] = rv[k];
     } else {
         const R beta = (R)st.beta;
         cx<typename Spinor<PPP>::R> q[12];
-        Spinor<PPP>::load(p, e, q);
+        Spinor<PPP>::load(pf, i, q);
 #pragma unroll
         for (int k = 0; k < 12; ++k)
             pv[k] = {rv[k].re + beta * (R)q[k].re, rv[k].im + beta * (R)q[k].im};
@@ -279,31 +302,30 @@ __global__ void k_update_p(FieldRef p, FieldRef r, Gate gate) {
     cx<typename Spinor<PPP>::R> o[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) o[k] = {(typename Spinor<PPP>::R)pv[k].re, (typename Spinor<PPP>::R)pv[k].im};
-    Spinor<PPP>::store(p, e, o);
+    Spinor<PPP>::store(pf, i, o);
 }
 
 void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const RedArgs &red,
                       Gate gate, hipStream_t s) {
-    const int bs = block_for_nrhs(x.nrhs);
-    const int nb = blocks_for(x.n, bs);
+    const dim3 gr = field_grid(x), bs(kSiteBlock);
     if (x.prec == WD_F64)
-        hipLaunchKernelGGL((k_update_xr<WD_F64, WD_F64>), dim3(nb), dim3(bs), 0, s, x, r, p, Ap, red, gate);
+        hipLaunchKernelGGL((k_update_xr<WD_F64, WD_F64>), gr, bs, 0, s, x, r, p, Ap, red, gate);
     else if (p.prec == WD_F32)
-        hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F32>), dim3(nb), dim3(bs), 0, s, x, r, p, Ap, red, gate);
+        hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F32>), gr, bs, 0, s, x, r, p, Ap, red, gate);
     else
-        hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F16>), dim3(nb), dim3(bs), 0, s, x, r, p, Ap, red, gate);
-    launch_finalize(red, nb, true, s);
+        hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F16>), gr, bs, 0, s, x, r, p, Ap, red, gate);
+    launch_finalize(red, gr.x, true, s);
 }
 
 template <bool RESTART>
 static void update_p_impl(FieldRef p, FieldRef r, Gate gate, hipStream_t s) {
-    const int nb = blocks_for(p.n, kBS);
+    const dim3 gr = field_grid(p), bs(kSiteBlock);
     if (r.prec == WD_F64)
-        hipLaunchKernelGGL((k_update_p<WD_F64, WD_F64, RESTART>), dim3(nb), dim3(kBS), 0, s, p, r, gate);
+        hipLaunchKernelGGL((k_update_p<WD_F64, WD_F64, RESTART>), gr, bs, 0, s, p, r, gate);
     else if (p.prec == WD_F32)
-        hipLaunchKernelGGL((k_update_p<WD_F32, WD_F32, RESTART>), dim3(nb), dim3(kBS), 0, s, p, r, gate);
+        hipLaunchKernelGGL((k_update_p<WD_F32, WD_F32, RESTART>), gr, bs, 0, s, p, r, gate);
     else
-        hipLaunchKernelGGL((k_update_p<WD_F32, WD_F16, RESTART>), dim3(nb), dim3(kBS), 0, s, p, r, gate);
+        hipLaunchKernelGGL((k_update_p<WD_F32, WD_F16, RESTART>), gr, bs, 0, s, p, r, gate);
 }
 
 void launch_update_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s) {
@@ -318,50 +340,49 @@ void launch_restart_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s) {
 
 // r = b - Ax (Ax absent: r = b), float64; reduce |r|^2
 __global__ void k_residual(FieldRef r, FieldRef b, FieldRef Ax, RedArgs red) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nrhs = r.nrhs;
+    const int rhs = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double nrm = 0.0;
-    if (e < r.n) {
+    if (i < r.V) {
         cx<double> bv[12];
-        Spinor<WD_F64>::load(b, e, bv);
+        Spinor<WD_F64>::load(rhs_view(b, rhs), i, bv);
         if (Ax.data) {
             cx<double> av[12];
-            Spinor<WD_F64>::load(Ax, e, av);
+            Spinor<WD_F64>::load(rhs_view(Ax, rhs), i, av);
 #pragma unroll
             for (int k = 0; k < 12; ++k) bv[k] = bv[k] - av[k];
         }
 #pragma unroll
         for (int k = 0; k < 12; ++k) nrm += bv[k].re * bv[k].re + bv[k].im * bv[k].im;
-        Spinor<WD_F64>::store(r, e, bv);
+        Spinor<WD_F64>::store(rhs_view(r, rhs), i, bv);
     }
-    reduce_block(nrm, red.partials, nrhs);
+    reduce_block(nrm, red.partials, (size_t)blockIdx.x * r.nrhs + rhs);
 }
 
 template <int PREC>
 __global__ void k_norm(FieldRef f, RedArgs red) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rhs = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double nrm = 0.0;
-    if (e < f.n) {
+    if (i < f.V) {
         cx<double> v[12];
-        load_as_double<PREC>(f, e, v);
+        load_as_double<PREC>(rhs_view(f, rhs), i, v);
 #pragma unroll
         for (int k = 0; k < 12; ++k) nrm += v[k].re * v[k].re + v[k].im * v[k].im;
     }
-    reduce_block(nrm, red.partials, f.nrhs);
+    reduce_block(nrm, red.partials, (size_t)blockIdx.x * f.nrhs + rhs);
 }
 
 void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, hipStream_t s) {
-    const int bs = block_for_nrhs(r.nrhs);
-    const int nb = blocks_for(r.n, bs);
-    hipLaunchKernelGGL(k_residual, dim3(nb), dim3(bs), 0, s, r, b, Ax, red);
-    launch_finalize(red, nb, false, s);
+    const dim3 gr = field_grid(r);
+    hipLaunchKernelGGL(k_residual, gr, dim3(kSiteBlock), 0, s, r, b, Ax, red);
+    launch_finalize(red, gr.x, false, s);
 }
 
 void launch_norm(FieldRef f, const RedArgs &red, hipStream_t s) {
-    const int bs = block_for_nrhs(f.nrhs);
-    const int nb = blocks_for(f.n, bs);
-    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_norm<PP>, dim3(nb), dim3(bs), 0, s, f, red));
-    launch_finalize(red, nb, false, s);
+    const dim3 gr = field_grid(f);
+    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_norm<PP>, gr, dim3(kSiteBlock), 0, s, f, red));
+    launch_finalize(red, gr.x, false, s);
 }
 
 __global__ void k_init_state(RhsState *st, BatchState *batch, int nrhs) {

@@ -46,6 +46,25 @@ __device__ __forceinline__ R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; 
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// vector load / store; NT: non-temporal (streamed data that should not
+// displace reused data in the caches)
+template <bool NT, typename T>
+__device__ __forceinline__ T ldv(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void stv(T *p, T v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
 
 // ------------------------------------------------------------------ tiles
 
@@ -56,6 +75,13 @@ __device__ __forceinline__ const char *tile_elem(const void *base, size_t tile_b
 }
 
 // ------------------------------------------------------------------ spinors
+
+// the field of one right-hand side: entries are then site indices
+__device__ __forceinline__ FieldRef rhs_view(FieldRef f, int rhs) {
+    f.data = (char *)f.data + (size_t)rhs * (size_t)(f.stride >> 6) * spinor_tile_bytes(f.prec);
+    f.nrhs = 1;
+    return f;
+}
 
 template <int PREC>
 struct Spinor;
@@ -71,10 +97,11 @@ struct Spinor<WD_F64> {
             v[k] = {d.x, d.y};
         }
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-            *(double2 *)tile_elem(f.data, kTileBytes, i, k) = make_double2(v[k].re, v[k].im);
+            stv<NT>((d2_t *)tile_elem(f.data, kTileBytes, i, k), d2_t{v[k].re, v[k].im});
     }
 };
 
@@ -90,11 +117,12 @@ struct Spinor<WD_F32> {
             v[2 * j + 1] = {q.z, q.w};
         }
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
 #pragma unroll
         for (int j = 0; j < 6; ++j)
-            *(float4 *)tile_elem(f.data, kTileBytes, i, j) =
-                make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
+            stv<NT>((f4_t *)tile_elem(f.data, kTileBytes, i, j),
+                    f4_t{v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im});
     }
 };
 
@@ -116,6 +144,7 @@ struct Spinor<WD_F16> {
                 v[4 * j + m] = {s * (float)q[2 * m], s * (float)q[2 * m + 1]};
         }
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void store(const FieldRef &f, int i, const cx<R> v[12]) {
         float mx = 0.f;
 #pragma unroll
@@ -129,9 +158,9 @@ struct Spinor<WD_F16> {
                 q[2 * m] = (_Float16)(v[4 * j + m].re * inv);
                 q[2 * m + 1] = (_Float16)(v[4 * j + m].im * inv);
             }
-            *(h8_t *)tile_elem(f.data, kTileBytes, i, j) = q;
+            stv<NT>((h8_t *)tile_elem(f.data, kTileBytes, i, j), q);
         }
-        *(float *)scale_ptr(f, i) = mx;
+        stv<NT>((float *)scale_ptr(f, i), mx);
     }
 };
 
@@ -155,10 +184,11 @@ template <>
 struct Link<WD_F64> {
     using R = double;
     static constexpr size_t kTileBytes = 36 * 1024;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            double2 d = *(const double2 *)tile_elem(g, kTileBytes, s, mu * 9 + k);
+            const d2_t d = ldv<NT>((const d2_t *)tile_elem(g, kTileBytes, s, mu * 9 + k));
             u[k] = {d.x, d.y};
         }
     }
@@ -173,10 +203,11 @@ template <>
 struct Link<WD_F32> {
     using R = float;
     static constexpr size_t kTileBytes = 12 * 1024;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            float4 q = *(const float4 *)tile_elem(g, kTileBytes, s, mu * 3 + j);
+            const f4_t q = ldv<NT>((const f4_t *)tile_elem(g, kTileBytes, s, mu * 3 + j));
             u[2 * j] = {q.x, q.y};
             u[2 * j + 1] = {q.z, q.w};
         }
@@ -198,10 +229,11 @@ struct Link<WD_F16> {
     static __device__ __forceinline__ const char *elem(const void *g, int mu, int s, int j) {
         return (const char *)g + (size_t)(s >> 6) * kTileBytes + (mu * 3 + j) * 512 + (s & 63) * 8;
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            h4_t q = *(const h4_t *)elem(g, mu, s, j);
+            const h4_t q = ldv<NT>((const h4_t *)elem(g, mu, s, j));
             u[2 * j] = {(float)q[0], (float)q[1]};
             u[2 * j + 1] = {(float)q[2], (float)q[3]};
         }
@@ -225,10 +257,10 @@ struct Link<WD_F16> {
 // ------------------------------------------------------------------ reduction
 //
 // Deterministic and split in two launches: every block of the producing
-// kernel reduces its contribution (a fixed butterfly inside each wave for
-// nrhs == 1, a fixed LDS tree over site slots for nrhs > 1) and writes one
-// partial per rhs; a one-block finalize kernel then sums the partials in a
-// fixed order and updates the solver state.  The kernel boundary orders the
+// kernel reduces its contribution (one rhs per block: a fixed butterfly
+// inside each wave, then the waves in order) and writes one partial; a
+// one-block finalize kernel then sums the partials of each rhs in a fixed
+// order and updates the solver state.  The kernel boundary orders the
 // two phases, so no device-scope fence (an L2 write-back on this chip) is
 // issued per block.  Results are bitwise reproducible for a launch shape.
 
@@ -333,32 +365,20 @@ __device__ inline void recount_batch(const RedArgs &red) {
 }
 
 // Phase 1.  v: this thread's contribution (0 for idle threads).  Must be
-// reached by every thread of the block.  blockDim.x = S * nrhs with S a power
-// of two and the block's first entry a multiple of nrhs, so thread t belongs
-// to rhs t % nrhs.  Writes partials[blockIdx.x * nrhs + rhs].
-__device__ inline void reduce_block(double v, double *partials, int nrhs) {
-    __shared__ double sm[256];
+// reached by every thread of the block; blockDim.x is a multiple of 64.  A
+// fixed butterfly inside each wave, then wave sums in order; writes
+// partials[idx].
+__device__ inline void reduce_block(double v, double *partials, size_t idx) {
+    __shared__ double sm[16];
     const int tid = threadIdx.x;
-    const int bd = blockDim.x;
-    if (nrhs == 1) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if ((tid & 63) == 0) sm[tid >> 6] = v;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < (bd >> 6); ++w) s += sm[w];
-            partials[blockIdx.x] = s;
-        }
-    } else {
-        const int S = bd / nrhs;
-        sm[tid] = v;
-        __syncthreads();
-        for (int stride = S >> 1; stride > 0; stride >>= 1) {
-            if (tid < stride * nrhs) sm[tid] += sm[tid + stride * nrhs];
-            __syncthreads();
-        }
-        if (tid < nrhs) partials[(size_t)blockIdx.x * nrhs + tid] = sm[tid];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((tid & 63) == 0) sm[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sm[w];
+        partials[idx] = s;
     }
 }
 

@@ -1,6 +1,6 @@
 // Wilson-Dirac stencil (Eq. (1) of Sec. 2.1 with the minus sign) on gfx950.
 //
-// One lane per (site, rhs) entry.  Each of the eight hops projects the
+// One lane per site of one right-hand side.  Each of the eight hops projects the
 // neighbour spinor to a half-spinor with 1 -+ gamma_mu (two spin components
 // of three colours; the projectors have rank 2, Sec. 2.1), multiplies the two
 // colour vectors by U_mu(x) (forward) or U_mu(x-mu)^dag (backward), and
@@ -30,6 +30,15 @@
 #endif
 #ifndef WD_GROUP_LO
 #define WD_GROUP_LO 2
+#endif
+// non-temporal forward links / outputs in the marching stencil (measured:
+// streaming the outputs past the caches keeps more of the slices the
+// neighbouring columns read; the links are re-read by the backward hops)
+#ifndef WD_NT_LINK
+#define WD_NT_LINK 0
+#endif
+#ifndef WD_NT_OUT
+#define WD_NT_OUT 1
 #endif
 
 namespace wd {
@@ -141,14 +150,10 @@ __device__ __forceinline__ int logical_block() {
 #endif
 }
 
-// one hop with the link already in registers
-template <int MU, int S, bool BWD, int PREC>
-__device__ __forceinline__ void hop_u(const cx<typename Spinor<PREC>::R> u[9], const FieldRef &in,
-                                      int nbr_entry, bool negate,
-                                      cx<typename Spinor<PREC>::R> acc[12]) {
-    using R = typename Spinor<PREC>::R;
-    cx<R> p[12];
-    Spinor<PREC>::load(in, nbr_entry, p);
+// one hop with the neighbour spinor and the link already in registers
+template <int MU, int S, bool BWD, typename R>
+__device__ __forceinline__ void hop_p(const cx<R> p[12], const cx<R> u[9], bool negate,
+                                      cx<R> acc[12]) {
     cx<R> h0[3], h1[3];
     project<MU, S>(p, h0, h1);
     const R sg = negate ? R(-1) : R(1);
@@ -163,20 +168,87 @@ __device__ __forceinline__ void hop_u(const cx<typename Spinor<PREC>::R> u[9], c
     accumulate<MU, S>(w0, w1, acc);
 }
 
+// LDS image of a workgroup's part of a brick slice: its tiles copied
+// verbatim (a part is a multiple of 64 sites and starts at a multiple of
+// 64), so the field accessors read it with the field's own tile arithmetic.
+template <int PREC>
+__host__ __device__ inline size_t slice_bytes(int sites) {
+    return (size_t)(sites >> 6) * Spinor<PREC>::kTileBytes;
+}
+
+// field view of an LDS slice image
+__device__ __forceinline__ FieldRef lds_view(const FieldRef &f, const char *img) {
+    FieldRef v = f;
+    v.data = (void *)img;
+    return v;
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Asynchronous copy of the slice whose first tile is tile0 into the LDS image
+// img: wave w copies tile w, plane by plane, each lane 16 bytes (4 for the
+// binary16 scales) straight from memory into LDS (the wave's LDS target is
+// uniform, lane k lands at k * size past it).  Completion is tracked by the
+// vector memory counter.
+template <int PREC>
+__device__ __forceinline__ void slice_copy(const FieldRef &f, int tile0, char *img) {
+    constexpr size_t TB = Spinor<PREC>::kTileBytes;
+    constexpr int NP = PREC == WD_F64 ? 12 : (PREC == WD_F32 ? 6 : 3);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
+    const char *src = (const char *)f.data + (size_t)(tile0 + w) * TB;
+    char *dst = img + (size_t)w * TB;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        __builtin_amdgcn_global_load_lds((const void *)(src + k * 1024 + lane * 16),
+                                         (lds_void *)(dst + k * 1024), 16, 0, 0);
+    if (PREC == WD_F16)
+        __builtin_amdgcn_global_load_lds((const void *)(src + NP * 1024 + lane * 4),
+                                         (lds_void *)(dst + NP * 1024), 4, 0, 0);
+}
+
+// one spatial hop of the marching stencil: the neighbour comes from the LDS
+// image when it lies in this workgroup's part of the slice (wvol sites from
+// sbase), else (a brick face, or another part of the slice) from memory
+template <int MU, int S, bool BWD, int PREC>
+__device__ __forceinline__ void hop_s(const void *gauge, const FieldRef &in, const FieldRef &cur,
+                                      int sbase, int wvol, int nbr, int link_site,
+                                      cx<typename Spinor<PREC>::R> acc[12]) {
+    using R = typename Spinor<PREC>::R;
+    cx<R> p[12];
+    const int d = nbr - sbase;
+    if ((unsigned)d < (unsigned)wvol)
+        Spinor<PREC>::load(cur, d, p);
+    else
+        Spinor<PREC>::load(in, nbr, p);
+    cx<R> h0[3], h1[3];
+    project<MU, S>(p, h0, h1);
+    cx<R> u[9];
+    Link<PREC>::template load<WD_NT_LINK && !BWD>(gauge, MU, link_site, u);
+    cx<R> w0[3], w1[3];
+    su3_mul<BWD>(u, h0, w0);
+    su3_mul<BWD>(u, h1, w1);
+    accumulate<MU, S>(w0, w1, acc);
+}
+
 template <int PREC, bool DAG, bool RED, int GROUP>
 __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__ gauge, FieldRef in,
                                                 FieldRef out, double kappa_d, RedArgs red,
                                                 Gate gate) {
     using R = typename Spinor<PREC>::R;
     if (gate.batch && gate.batch->n_active == 0) return;  // grid-uniform
+    // logical block = site block * nrhs + rhs: the workgroups of all rhs on
+    // the same sites are neighbours in the XCD's run and share its L2 links
     const int nrhs = in.nrhs;
-    const int e = logical_block() * blockDim.x + threadIdx.x;
-    bool live = e < in.n;
-    const int site = e / nrhs;
-    const int rhs = e - site * nrhs;
-    if (live && gate.st && !gate.st[rhs].active) live = false;
+    const int lb = logical_block();
+    const int sb = lb / nrhs;
+    const int rhs = lb - sb * nrhs;
+    // a frozen rhs: the finaliser ignores its partials
+    if (gate.st && !gate.st[rhs].active) return;  // workgroup-uniform
+    const FieldRef fin = rhs_view(in, rhs);
+    const int site = sb * blockDim.x + threadIdx.x;
     double nrm = 0.0;
-    if (live) {
+    if (site < g.V) {
         const Nbrs nb = neighbours(g, site);
         const int xp = nb.xp, xm = nb.xm, yp = nb.yp, ym = nb.ym;
         const int zp = nb.zp, zm = nb.zm, tp = nb.tp, tm = nb.tm;
@@ -194,143 +266,193 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
         // memory-level parallelism).
 #define WD_HOP_FENCE(k) \
     if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
-        hop<0, SF, false, PREC>(gauge, in, xp * nrhs + rhs, site, false, acc);
+        hop<0, SF, false, PREC>(gauge, fin, xp, site, false, acc);
         WD_HOP_FENCE(1);
-        hop<0, SB, true, PREC>(gauge, in, xm * nrhs + rhs, xm, false, acc);
+        hop<0, SB, true, PREC>(gauge, fin, xm, xm, false, acc);
         WD_HOP_FENCE(2);
-        hop<1, SF, false, PREC>(gauge, in, yp * nrhs + rhs, site, false, acc);
+        hop<1, SF, false, PREC>(gauge, fin, yp, site, false, acc);
         WD_HOP_FENCE(3);
-        hop<1, SB, true, PREC>(gauge, in, ym * nrhs + rhs, ym, false, acc);
+        hop<1, SB, true, PREC>(gauge, fin, ym, ym, false, acc);
         WD_HOP_FENCE(4);
-        hop<2, SF, false, PREC>(gauge, in, zp * nrhs + rhs, site, false, acc);
+        hop<2, SF, false, PREC>(gauge, fin, zp, site, false, acc);
         WD_HOP_FENCE(5);
-        hop<2, SB, true, PREC>(gauge, in, zm * nrhs + rhs, zm, false, acc);
+        hop<2, SB, true, PREC>(gauge, fin, zm, zm, false, acc);
         WD_HOP_FENCE(6);
-        hop<3, SF, false, PREC>(gauge, in, tp * nrhs + rhs, site, neg_tp, acc);
+        hop<3, SF, false, PREC>(gauge, fin, tp, site, neg_tp, acc);
         WD_HOP_FENCE(7);
-        hop<3, SB, true, PREC>(gauge, in, tm * nrhs + rhs, tm, neg_tm, acc);
+        hop<3, SB, true, PREC>(gauge, fin, tm, tm, neg_tm, acc);
         WD_HOP_FENCE(8);
 #undef WD_HOP_FENCE
 
         cx<R> c[12];
-        Spinor<PREC>::load(in, e, c);
+        Spinor<PREC>::load(fin, site, c);
         const R kappa = (R)kappa_d;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             c[k] = c[k] - scale(kappa, acc[k]);
             if (RED) nrm += (double)c[k].re * (double)c[k].re + (double)c[k].im * (double)c[k].im;
         }
-        Spinor<PREC>::store(out, e, c);
+        Spinor<PREC>::store(rhs_view(out, rhs), site, c);
     }
-    if (RED) reduce_block(nrm, red.partials, nrhs);
+    if (RED) reduce_block(nrm, red.partials, (size_t)sb * nrhs + rhs);
 }
 
 
-// Time-marching stencil (nrhs == 1).  One workgroup per brick column and
-// chunk of time slices, one lane per brick site.  The workgroup steps
-// through its time slices together, so the x/y/z neighbours a lane reads
-// were fetched by its neighbour lanes moments earlier, and the backward t
-// hop U_t(x, t-1)^dag (1 -+ gamma_t) psi(x, t-1) is carried from the previous
-// slice in registers instead of being reloaded.  Blocks are ordered chunk
-// major, so each XCD's contiguous block run covers one band of time slices
-// of many neighbouring columns (their shared brick faces stay in its L2).
+// Time-marching stencil.  One workgroup per brick column, chunk of time
+// slices, part of the brick slice (all of it, or a contiguous half or
+// quarter) and rhs, one lane per site.  The workgroup steps through its
+// slices together with two LDS images of its part:
+//  - at the start of step t the next slice t+1 is copied from memory into
+//    the spare image, while the x/y/z hops of slice t read their neighbours
+//    from the current image (inside the part) or from memory (across a
+//    brick face or into another part);
+//  - the forward t hop reads psi(t+1) from the new image, which is the
+//    current one of the next step, so every site of the column is read from
+//    memory once;
+//  - the backward t hop U_t(x, t-1)^dag (1 -+ gamma_t) psi(x, t-1) is carried
+//    from the previous step in registers.
+// The hops are summed in the order of the one-lane-per-site kernel.
+// Logical blocks are ordered chunk, column, rhs (rhs fastest), so each XCD's
+// contiguous run covers one band of time slices of many neighbouring columns
+// (their shared brick faces stay in its L2), and the workgroups of all rhs
+// of a column run side by side and read its links from L2 after the first.
+// The fused reduction writes one partial per (column, slice, part, rhs), so
+// its summation order does not depend on the chunk length or on nrhs.
 template <int PREC, bool DAG, bool RED, int GROUP>
-__global__ void __launch_bounds__(256) k_dslash_tm(Geom g, const void *__restrict__ gauge,
+__global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *__restrict__ gauge,
                                                    FieldRef in, FieldRef out, double kappa_d,
                                                    RedArgs red, Gate gate, int tchunk,
                                                    int ncols) {
     using R = typename Spinor<PREC>::R;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ double wsum[kTmMaxBlock / 64];
     if (gate.batch && gate.batch->n_active == 0) return;  // grid-uniform
-    const int b = logical_block();
-    const int chunk = b / ncols;
-    const int col = b - chunk * ncols;
-    const int Lt = g.L[3];
+    const int nrhs = in.nrhs;
+    const int wvol = (int)blockDim.x;  // sites of this workgroup's part of a slice
+    const int nsub = g.bvol / wvol;
+    const int lb = logical_block();
+    const int cb = lb / nrhs;
+    const int rhs = lb - cb * nrhs;
+    // a frozen rhs: the finaliser ignores its partials
+    if (gate.st && !gate.st[rhs].active) return;  // workgroup-uniform
+    const FieldRef fin = rhs_view(in, rhs), fout = rhs_view(out, rhs);
+    const int cc = cb / nsub;
+    const int h = cb - cc * nsub;
+    const int chunk = cc / ncols;
+    const int col = cc - chunk * ncols;
+    const int Lt = g.L[3], bvol = g.bvol;
+    const int l = (int)threadIdx.x;
     const int t0 = chunk * tchunk;
     const int t1 = t0 + tchunk < Lt ? t0 + tchunk : Lt;
-    const bool live = !gate.st || gate.st[0].active;  // uniform (one rhs)
+    // first site of this workgroup's part of slice t: cbase + t * bvol
+    const int cbase = col * Lt * bvol + h * wvol;
+    char *img0 = lds;
+    char *img1 = lds + slice_bytes<PREC>(wvol);
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     const R kappa = (R)kappa_d;
-    double nrm = 0.0;
-    if (live) {
-        const int base = col * Lt * g.bvol + (int)threadIdx.x;
-        // carried backward t hop for the first slice: from t0 - 1
-        cx<R> cw0[3], cw1[3];
-        {
-            const int tprev = t0 == 0 ? Lt - 1 : t0 - 1;
-            const int ip = base + tprev * g.bvol;
-            cx<R> p[12];
-            Spinor<PREC>::load(in, ip, p);
-            cx<R> h0[3], h1[3];
-            project<3, SB>(p, h0, h1);
-            const R sg = (g.antiperiodic && t0 == 0) ? R(-1) : R(1);
+
+    // prologue: slice t0 into image 0, and the backward t hop from t0 - 1
+    slice_copy<PREC>(fin, (cbase + t0 * bvol) >> 6, img0);
+    cx<R> cw0[3], cw1[3];
+    {
+        const int tprev = t0 == 0 ? Lt - 1 : t0 - 1;
+        const int ip = cbase + tprev * bvol + l;
+        cx<R> p[12];
+        Spinor<PREC>::load(fin, ip, p);
+        cx<R> h0[3], h1[3];
+        project<3, SB>(p, h0, h1);
+        const R sg = (g.antiperiodic && t0 == 0) ? R(-1) : R(1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                h0[c] = scale(sg, h0[c]);
-                h1[c] = scale(sg, h1[c]);
-            }
-            cx<R> u[9];
-            Link<PREC>::load(gauge, 3, ip, u);
-            su3_mul<true>(u, h0, cw0);
-            su3_mul<true>(u, h1, cw1);
+        for (int c = 0; c < 3; ++c) {
+            h0[c] = scale(sg, h0[c]);
+            h1[c] = scale(sg, h1[c]);
         }
-        for (int t = t0; t < t1; ++t) {
-            const int i = base + t * g.bvol;
-            const Nbrs nb = neighbours(g, i);
-            cx<R> acc[12];
+        cx<R> u[9];
+        Link<PREC>::load(gauge, 3, ip, u);
+        su3_mul<true>(u, h0, cw0);
+        su3_mul<true>(u, h1, cw1);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int t = t0; t < t1; ++t) {
+        const bool odd = (t - t0) & 1;
+        const FieldRef cur = lds_view(fin, odd ? img1 : img0);
+        const FieldRef nxt = lds_view(fin, odd ? img0 : img1);
+        const int tn = t + 1 < Lt ? t + 1 : 0;
+        slice_copy<PREC>(fin, (cbase + tn * bvol) >> 6, (char *)nxt.data);
+        const int sbase = cbase + t * bvol;
+        const int i = sbase + l;
+        const Nbrs nb = neighbours(g, i);
+        cx<R> acc[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
 #define WD_HOP_FENCE(k) \
     if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
-            hop<0, SF, false, PREC>(gauge, in, nb.xp, i, false, acc);
-            WD_HOP_FENCE(1);
-            hop<0, SB, true, PREC>(gauge, in, nb.xm, nb.xm, false, acc);
-            WD_HOP_FENCE(2);
-            hop<1, SF, false, PREC>(gauge, in, nb.yp, i, false, acc);
-            WD_HOP_FENCE(3);
-            hop<1, SB, true, PREC>(gauge, in, nb.ym, nb.ym, false, acc);
-            WD_HOP_FENCE(4);
-            hop<2, SF, false, PREC>(gauge, in, nb.zp, i, false, acc);
-            WD_HOP_FENCE(5);
-            hop<2, SB, true, PREC>(gauge, in, nb.zm, nb.zm, false, acc);
-            WD_HOP_FENCE(6);
-            cx<R> ut[9];
-            Link<PREC>::load(gauge, 3, i, ut);
-            hop_u<3, SF, false, PREC>(ut, in, nb.tp, g.antiperiodic && nb.cross_tp, acc);
-            WD_HOP_FENCE(7);
+        hop_s<0, SF, false, PREC>(gauge, fin, cur, sbase, wvol, nb.xp, i, acc);
+        WD_HOP_FENCE(1);
+        hop_s<0, SB, true, PREC>(gauge, fin, cur, sbase, wvol, nb.xm, nb.xm, acc);
+        WD_HOP_FENCE(2);
+        hop_s<1, SF, false, PREC>(gauge, fin, cur, sbase, wvol, nb.yp, i, acc);
+        WD_HOP_FENCE(3);
+        hop_s<1, SB, true, PREC>(gauge, fin, cur, sbase, wvol, nb.ym, nb.ym, acc);
+        WD_HOP_FENCE(4);
+        hop_s<2, SF, false, PREC>(gauge, fin, cur, sbase, wvol, nb.zp, i, acc);
+        WD_HOP_FENCE(5);
+        hop_s<2, SB, true, PREC>(gauge, fin, cur, sbase, wvol, nb.zm, nb.zm, acc);
+        WD_HOP_FENCE(6);
 #undef WD_HOP_FENCE
-            accumulate<3, SB>(cw0, cw1, acc);
-            cx<R> c[12];
-            Spinor<PREC>::load(in, i, c);
-            // carry for slice t + 1 (never crosses the boundary inside a chunk)
-            {
-                cx<R> h0[3], h1[3];
-                project<3, SB>(c, h0, h1);
-                su3_mul<true>(ut, h0, cw0);
-                su3_mul<true>(ut, h1, cw1);
-            }
+        cx<R> ut[9];
+        Link<PREC>::template load<WD_NT_LINK>(gauge, 3, i, ut);
+        // the next slice has landed in LDS (every wave's copy)
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        {
+            cx<R> nx[12];
+            Spinor<PREC>::load(nxt, l, nx);
+            hop_p<3, SF, false>(nx, ut, g.antiperiodic && t == Lt - 1, acc);
+        }
+        accumulate<3, SB>(cw0, cw1, acc);
+        cx<R> c[12];
+        Spinor<PREC>::load(cur, l, c);
+        // carry for slice t + 1 (never crosses the boundary inside a chunk)
+        {
+            cx<R> h0[3], h1[3];
+            project<3, SB>(c, h0, h1);
+            su3_mul<true>(ut, h0, cw0);
+            su3_mul<true>(ut, h1, cw1);
+        }
+        double nrm = 0.0;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                c[k] = c[k] - scale(kappa, acc[k]);
-                if (RED) nrm += (double)c[k].re * (double)c[k].re + (double)c[k].im * (double)c[k].im;
-            }
-            Spinor<PREC>::store(out, i, c);
-            __syncthreads();  // keep the brick in step
+        for (int k = 0; k < 12; ++k) {
+            c[k] = c[k] - scale(kappa, acc[k]);
+            if (RED) nrm += (double)c[k].re * (double)c[k].re + (double)c[k].im * (double)c[k].im;
+        }
+        Spinor<PREC>::template store<WD_NT_OUT>(fout, i, c);
+        if (RED) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+            if ((l & 63) == 0) wsum[l >> 6] = nrm;
+        }
+        __syncthreads();  // the current image is free for the next copy
+        if (RED && l == 0) {
+            double s = 0.0;
+            for (int w = 0; w < (wvol >> 6); ++w) s += wsum[w];
+            red.partials[(((size_t)col * Lt + t) * nsub + h) * nrhs + rhs] = s;
         }
     }
-    if (RED) reduce_block(nrm, red.partials, 1);
 }
 
 // WD_TCHUNK overrides the marching stencil's chunk length (tuning)
-static int tm_chunk(const Geom &g) {
+static int tm_chunk(const Geom &g, int nrhs) {
     static const int env = [] {
         const char *e = getenv("WD_TCHUNK");
         return e ? atoi(e) : 0;
     }();
-    return tm_chunk_len(g, env);
+    return tm_chunk_len(g, nrhs, env);
 }
 
-// WD_SITE_KERNEL=1 forces the one-lane-per-entry stencil everywhere (tuning)
+// WD_SITE_KERNEL=1 forces the one-lane-per-site stencil everywhere (tuning)
 static const bool g_force_site_kernel = [] {
     const char *e = getenv("WD_SITE_KERNEL");
     return e && atoi(e) != 0;
@@ -342,59 +464,91 @@ struct HopGroup {
     static constexpr int value = PREC == WD_F64 ? WD_GROUP_F64 : WD_GROUP_LO;
 };
 
+// LDS a workgroup may use on the current device
+static size_t max_lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return (size_t)v;
+}
+
+// dynamic LDS above 64 KiB must be allowed per kernel once
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
+template <int PREC>
+static bool tm_fits(const Geom &g) {
+    static const size_t cap = max_lds_per_block();
+    return 2 * slice_bytes<PREC>(tm_wvol(g, PREC)) + 64 <= cap;
+}
+
+template <int PREC, bool DAG, bool RED>
+static void launch_tm_k(dim3 grid, dim3 bs, size_t lds, hipStream_t s, const Geom &g,
+                        const void *gauge, FieldRef in, FieldRef out, double kappa,
+                        const RedArgs &r, Gate gate, int tch, int ncols) {
+    constexpr int G = HopGroup<PREC>::value;
+    auto k = k_dslash_tm<PREC, DAG, RED, G>;
+    allow_lds(k, lds);
+    hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+}
+
 template <int PREC>
 static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                       FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
-    const int tch = tm_chunk(g);
+    const int wvol = tm_wvol(g, PREC);
+    const int nsub = g.bvol / wvol;
+    const int tch = tm_chunk(g, in.nrhs * nsub);
     const int ncols = g.V / (g.L[3] * g.bvol);
-    const int nb = tm_blocks(g, tch);
-    const int bs = g.bvol;
-    constexpr int G = HopGroup<PREC>::value;
+    const dim3 grid(tm_blocks(g, tch) * nsub * in.nrhs), bs(wvol);
+    const size_t lds = 2 * slice_bytes<PREC>(wvol);
     RedArgs r{};
     if (red) r = *red;
     if (dagger) {
         if (red)
-            hipLaunchKernelGGL((k_dslash_tm<PREC, true, true, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, true, true>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
         else
-            hipLaunchKernelGGL((k_dslash_tm<PREC, true, false, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, true, false>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
     } else {
         if (red)
-            hipLaunchKernelGGL((k_dslash_tm<PREC, false, true, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, false, true>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
         else
-            hipLaunchKernelGGL((k_dslash_tm<PREC, false, false, G>), dim3(nb), dim3(bs), 0, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, false, false>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
     }
-    if (red) launch_finalize(r, nb, gate.batch != nullptr, s);
+    // one partial per part of a brick slice: V / wvol of them per rhs
+    if (red) launch_finalize(r, g.V / wvol, gate.batch != nullptr, s);
 }
 
 template <int PREC>
 static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                         FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
-    // the marching stencil needs one partial per workgroup: use it only when
-    // the caller's partial buffer holds them (it always does when sized by
-    // reduce_partials_cap)
-    if (tm_eligible(g, in.nrhs) && !g_force_site_kernel &&
-        (!red || tm_blocks(g, tm_chunk(g)) <= red->partials_cap)) {
+    // the marching stencil writes one partial per workgroup: use it only
+    // when the caller's partial buffer holds them (it always does when sized
+    // by reduce_partials_cap)
+    if (tm_eligible(g) && tm_fits<PREC>(g) && !g_force_site_kernel &&
+        (!red || (int64_t)(g.V / tm_wvol(g, PREC)) * in.nrhs <= red->partials_cap)) {
         launch_tm<PREC>(g, gauge, kappa, dagger, in, out, red, gate, s);
         return;
     }
-    const int bs = block_for_nrhs(in.nrhs);
-    const int nb = blocks_for(in.n, bs);
+    const int nb = site_blocks(g.V);
+    const dim3 grid(nb * in.nrhs), bs(kSiteBlock);
     RedArgs r{};
     if (red) r = *red;
+    constexpr int G = HopGroup<PREC>::value;
     if (dagger) {
         if (red)
-            hipLaunchKernelGGL((k_dslash<PREC, true, true, HopGroup<PREC>::value>), dim3(nb), dim3(bs), 0, s, g, gauge, in,
-                               out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, true, true, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
         else
-            hipLaunchKernelGGL((k_dslash<PREC, true, false, HopGroup<PREC>::value>), dim3(nb), dim3(bs), 0, s, g, gauge,
-                               in, out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, true, false, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
     } else {
         if (red)
-            hipLaunchKernelGGL((k_dslash<PREC, false, true, HopGroup<PREC>::value>), dim3(nb), dim3(bs), 0, s, g, gauge,
-                               in, out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, false, true, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
         else
-            hipLaunchKernelGGL((k_dslash<PREC, false, false, HopGroup<PREC>::value>), dim3(nb), dim3(bs), 0, s, g, gauge,
-                               in, out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, false, false, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
     }
     if (red) launch_finalize(r, nb, gate.batch != nullptr, s);
 }

@@ -44,66 +44,11 @@ FieldRef carve(char *&cursor, int prec, int nrhs, int V) {
     FieldRef f{};
     f.prec = prec;
     f.nrhs = nrhs;
-    f.n = V * nrhs;
+    f.V = V;
+    f.stride = rhs_stride(V);
     f.data = cursor;
-    cursor += spinor_bytes(prec, f.n);
+    cursor += field_data_bytes(prec, V, nrhs);
     return f;
-}
-
-// Brick extents.  Preferred: tx * ty * tz a multiple of 64 and at most 256
-// (one brick per workgroup for the time-marching stencil), whole x rows
-// first (measured fastest at 48^3 x 96: full rows keep the x neighbours and
-// the backward x links inside the brick), then the largest volume.  Lattices too small
-// for that take whole x-rows with the largest y/z divisors up to 8 and 4.
-// WD_BRICK="tx,ty,tz" overrides the choice (tuning).
-static int largest_divisor_le(int n, int cap) {
-    for (int d = cap < n ? cap : n; d >= 1; --d)
-        if (n % d == 0) return d;
-    return 1;
-}
-
-void choose_bricks(Geom &g) {
-    int bx = 0, by = 0, bz = 0, best = 0;
-    for (int a = 1; a <= g.L[0]; ++a) {
-        if (g.L[0] % a) continue;
-        for (int b = 1; b <= g.L[1]; ++b) {
-            if (g.L[1] % b) continue;
-            for (int c = 1; c <= g.L[2]; ++c) {
-                if (g.L[2] % c) continue;
-                const int v = a * b * c;
-                if (v > 256 || v % 64) continue;
-                // prefer whole x rows, then volume, then y over z
-                const int score = (a == g.L[0] ? (1 << 24) : 0) + v * 4096 + a * 64 + b;
-                if (score > best) {
-                    best = score;
-                    bx = a;
-                    by = b;
-                    bz = c;
-                }
-            }
-        }
-    }
-    if (!best) {
-        bx = g.L[0];
-        by = largest_divisor_le(g.L[1], 8);
-        bz = largest_divisor_le(g.L[2], 4);
-    }
-    if (const char *e = getenv("WD_BRICK")) {
-        int a = 0, b = 0, c = 0;
-        if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && c >= 1 &&
-            g.L[0] % a == 0 && g.L[1] % b == 0 && g.L[2] % c == 0) {
-            bx = a;
-            by = b;
-            bz = c;
-        }
-    }
-    g.tx = bx;
-    g.ty = by;
-    g.tz = bz;
-    g.ncx = g.L[0] / bx;
-    g.ncy = g.L[1] / by;
-    g.ncz = g.L[2] / bz;
-    g.bvol = bx * by * bz;
 }
 
 void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err) {
@@ -282,7 +227,7 @@ int wd_field_create(wd_lattice *lat, int prec, int nrhs, wd_field **out) {
     if (nrhs < 1 || nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", nrhs);
     wd_field *f = new (std::nothrow) wd_field();
     if (!f) return fail(WD_ERR_NOMEM, "host allocation failed");
-    size_t bytes = spinor_bytes(prec, (int64_t)lat->g.V * nrhs);
+    size_t bytes = field_data_bytes(prec, lat->g.V, nrhs);
     hipError_t he = hipMalloc(&f->mem, bytes);
     if (he != hipSuccess) {
         delete f;
@@ -349,7 +294,7 @@ int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, cons
     void *g = gauge_for(lat, prec, s, &err);
     if (!g) return err;
     const int V = lat->g.V;
-    size_t one = spinor_bytes(prec, (int64_t)V * nrhs) + 256;
+    size_t one = field_data_bytes(prec, V, nrhs) + 256;
     void *mem = nullptr;
     hipError_t he = hipMallocAsync(&mem, 2 * one, s);
     if (he != hipSuccess)

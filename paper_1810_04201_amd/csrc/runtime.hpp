@@ -61,7 +61,6 @@ void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const 
             const FieldRef &out, const RedArgs *red, Gate gate, hipStream_t s);
 
 FieldRef carve(char *&cursor, int prec, int nrhs, int V);
-void choose_bricks(Geom &g);
 
 // ------------------------------------------------------------------ solve
 

@@ -70,14 +70,16 @@ int Solve::validate(wd_lattice *lat, const wd_solve_params *p) {
 
 static size_t align256(size_t b) { return (b + 255u) & ~(size_t)255u; }
 
-static size_t field_bytes(int prec, int64_t n) { return align256(spinor_bytes(prec, n)) + 256; }
+static size_t field_bytes(int prec, int V, int nrhs) {
+    return align256(field_data_bytes(prec, V, nrhs)) + 256;
+}
 
 size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
-    const int64_t n = (int64_t)lat->g.V * p.nrhs;
+    const int V = lat->g.V, nr = p.nrhs;
     const int lo = p.prec_inner;
     const int lo_xr = lo == WD_F16 ? WD_F32 : lo;
-    size_t b = 6 * field_bytes(WD_F64, n);
-    b += 2 * field_bytes(lo_xr, n) + 3 * field_bytes(lo, n);
+    size_t b = 6 * field_bytes(WD_F64, V, nr);
+    b += 2 * field_bytes(lo_xr, V, nr) + 3 * field_bytes(lo, V, nr);
     b += align256((size_t)reduce_partials_cap(lat->g, p.nrhs) * sizeof(double));
     b += align256(sizeof(RhsState) * 12) + 256;
     return b;
@@ -109,7 +111,7 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     auto next = [&](int prec) {
         char *c = cur;
         FieldRef f = carve(c, prec, nrhs, V);
-        cur += field_bytes(prec, n);
+        cur += field_bytes(prec, V, nrhs);
         return f;
     };
     b64_ = next(WD_F64);

@@ -6,6 +6,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 
 #include "wd.h"
 
@@ -23,7 +25,12 @@ namespace wd {
 // neighbour was touched one brick (bvol sites) earlier; x, y and z
 // neighbours are inside the brick except on its faces.
 //
-// Entries.  Spinor fields hold nrhs right-hand sides; entry e = i * nrhs + rhs.
+// Entries.  Spinor fields hold nrhs right-hand sides one after another, each
+// padded to whole tiles: entry e = rhs * stride + i with stride = V rounded
+// up to a multiple of 64.  Kernels take the right-hand side from the
+// workgroup index, so one workgroup touches one rhs, a frozen rhs costs its
+// workgroups nothing, and the workgroups of different rhs that share sites
+// (and therefore links) can be scheduled side by side.
 //
 // Tiles.  Every field is an array of tiles of 64 consecutive entries (sites
 // for links).  Inside a tile each component plane is one contiguous run of
@@ -47,7 +54,7 @@ constexpr int kTile = 64;   // entries per tile
 
 inline size_t tiles_of(int64_t n) { return (size_t)((n + kTile - 1) / kTile); }
 
-inline size_t spinor_tile_bytes(int prec) {
+__host__ __device__ inline size_t spinor_tile_bytes(int prec) {
     return prec == WD_F64 ? 12u * 1024u : (prec == WD_F32 ? 6u * 1024u : 3u * 1024u + 256u);
 }
 
@@ -140,9 +147,17 @@ __host__ __device__ inline Nbrs neighbours(const Geom &g, int i) {
 struct FieldRef {
     int prec;
     int nrhs;
-    int n;       // V * nrhs entries
+    int V;       // sites per rhs
+    int stride;  // entries per rhs: V rounded up to a multiple of 64
     void *data;  // tiles
 };
+
+inline int rhs_stride(int V) { return (int)(tiles_of(V) * kTile); }
+
+// bytes of a field of nrhs right-hand sides on V sites
+inline size_t field_data_bytes(int prec, int V, int nrhs) {
+    return tiles_of(V) * (size_t)nrhs * spinor_tile_bytes(prec);
+}
 
 // ------------------------------------------------------------------ solver state
 //
@@ -214,56 +229,137 @@ struct RedArgs {
     int mode;
 };
 
-// block size for nrhs right-hand sides: nrhs * S threads with S a power of
-// two and at most 256 threads, so every block holds all rhs of its sites and
-// the per-rhs tree reduction runs over S site slots.  Whole 64-wide waves for
-// nrhs in {1, 2, 3, 4, 6, 8, 12}; the last wave is partly idle otherwise.
-inline int block_for_nrhs(int nrhs) {
-    if (nrhs < 1 || nrhs > 12) return 0;
-    int S = 256;
-    while (S * nrhs > 256) S >>= 1;
-    return S * nrhs;
-}
-
 inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
 // ------------------------------------------------------------------ launch shapes
 //
-// The time-marching stencil (one right-hand side) runs one workgroup of bvol
-// lanes per brick column and chunk of time slices; every other reducing
-// kernel runs blocks_for(V * nrhs, block_for_nrhs(nrhs)) workgroups.  The
-// solver sizes its reduction partials from these same functions.
+// Field kernels run a grid of site_blocks(V) x nrhs workgroups of kSiteBlock
+// lanes (one lane per site of one rhs) and a reducing one writes a partial
+// per workgroup, at index site block * nrhs + rhs.  The time-marching stencil
+// runs one workgroup of w = tm_wvol lanes per brick column, chunk of time
+// slices, part h of the bvol / w parts of a brick slice, and rhs, and writes
+// a partial per part of a brick slice, at index
+// ((column * Lt + t) * (bvol / w) + h) * nrhs + rhs.  The solver sizes its
+// partial buffer from these same functions.
 
-inline bool tm_eligible(const Geom &g, int nrhs) {
-    return nrhs == 1 && g.bvol % 64 == 0 && g.bvol <= 256;
+constexpr int kSiteBlock = 256;
+
+inline int site_blocks(int V) { return blocks_for(V, kSiteBlock); }
+
+// largest brick (workgroup) of the time-marching stencil
+#ifndef WD_TM_MAXB
+#define WD_TM_MAXB 512
+#endif
+constexpr int kTmMaxBlock = WD_TM_MAXB;
+
+inline bool tm_eligible(const Geom &g) { return g.bvol % 64 == 0 && g.bvol <= kTmMaxBlock; }
+
+// sites per marching workgroup: a contiguous part of a brick slice (whole
+// multiples of 64).  float64 takes up to 384 (one workgroup per CU holds its
+// two LDS slice images); the float kernels run four waves per SIMD and do
+// best with at most 256.
+inline int tm_wvol(const Geom &g, int prec) {
+    const int cap = prec == WD_F64 ? 384 : 256;
+    int w = g.bvol;
+    while (w > cap && w % 128 == 0) w /= 2;
+    return w;
 }
 
-// time slices per chunk: enough workgroups to fill the chip (a multiple of
-// 8 chunks where the extent allows); env_chunk > 0 overrides (tuning)
-inline int tm_chunk_len(const Geom &g, int env_chunk) {
+// time slices per chunk: enough workgroups over all rhs to fill the chip (a
+// multiple of 8 chunks where the extent allows); env_chunk > 0 overrides
+// (tuning)
+inline int tm_chunk_len(const Geom &g, int nrhs, int env_chunk) {
     const int Lt = g.L[3];
     if (env_chunk > 0) return env_chunk < Lt ? env_chunk : Lt;
     const int ncols = g.V / (Lt * g.bvol);
     int nch = 8;
-    while (nch < Lt && ncols * nch < 2048) nch += 8;
+    while (nch < Lt && ncols * nch * nrhs < 2048) nch += 8;
     if (nch > Lt) nch = Lt;
     return (Lt + nch - 1) / nch;
 }
 
+// column chunks of the time-marching stencil (each runs bvol / w
+// workgroups per rhs)
 inline int tm_blocks(const Geom &g, int chunk_len) {
     const int ncols = g.V / (g.L[3] * g.bvol);
     return ncols * ((g.L[3] + chunk_len - 1) / chunk_len);
 }
 
 // partial sums any reducing launch on this geometry may write (the time
-// marching stencil uses at most V / 64 blocks whatever its chunk length)
+// marching stencil writes V / w <= V / 64 per rhs)
 inline int64_t reduce_partials_cap(const Geom &g, int nrhs) {
-    int64_t nb = blocks_for((int64_t)g.V * nrhs, block_for_nrhs(nrhs));
-    if (tm_eligible(g, nrhs)) {
+    int64_t nb = site_blocks(g.V);
+    if (tm_eligible(g)) {
         const int64_t tmb = (int64_t)g.V / 64;
         if (tmb > nb) nb = tmb;
     }
     return (nb + 1) * nrhs;
+}
+
+// ------------------------------------------------------------------ brick choice
+
+// Brick extents.  Preferred: whole x rows (the x neighbours and the
+// backward x links stay inside the brick), then the largest volume that is a
+// multiple of 64 (a brick slice is whole tiles): 384 sites where the lattice
+// has at least 256 brick columns to spread over the chip (float64 then
+// marches a whole 384-site slice per workgroup, the float kernels halves of
+// it: measured fastest at 48^3 x 96), else at most 256; then the fewest
+// neighbours across y/z brick faces per site (2/ty + 2/tz for a split
+// direction), then the thinner y extent.  Lattices too small for a 64-site
+// brick take whole x rows with the largest y/z divisors up to 8 and 4.
+// WD_BRICK="tx,ty,tz" overrides the choice (tuning).
+inline int largest_divisor_le(int n, int cap) {
+    for (int d = cap < n ? cap : n; d >= 1; --d)
+        if (n % d == 0) return d;
+    return 1;
+}
+
+inline void choose_bricks(Geom &g) {
+    int bx = 0, by = 0, bz = 0;
+    long long best = 0;
+    const bool big_ok = (long long)g.V / ((long long)g.L[3] * 384) >= 256;
+    for (int a = 1; a <= g.L[0]; ++a) {
+        if (g.L[0] % a) continue;
+        for (int b = 1; b <= g.L[1]; ++b) {
+            if (g.L[1] % b) continue;
+            for (int c = 1; c <= g.L[2]; ++c) {
+                if (g.L[2] % c) continue;
+                const int v = a * b * c;
+                if (v % 64 || (v > 256 && !(v == 384 && big_ok))) continue;
+                const int faces = (a < g.L[0] ? 240 / a : 0) + (b < g.L[1] ? 240 / b : 0) +
+                                  (c < g.L[2] ? 240 / c : 0);
+                const long long score = (a == g.L[0] ? (1LL << 40) : 0) + ((long long)v << 20) +
+                                        (long long)(2048 - faces) * 128 + (127 - b);
+                if (score > best) {
+                    best = score;
+                    bx = a;
+                    by = b;
+                    bz = c;
+                }
+            }
+        }
+    }
+    if (!best) {
+        bx = g.L[0];
+        by = largest_divisor_le(g.L[1], 8);
+        bz = largest_divisor_le(g.L[2], 4);
+    }
+    if (const char *e = getenv("WD_BRICK")) {
+        int a = 0, b = 0, c = 0;
+        if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && c >= 1 &&
+            g.L[0] % a == 0 && g.L[1] % b == 0 && g.L[2] % c == 0) {
+            bx = a;
+            by = b;
+            bz = c;
+        }
+    }
+    g.tx = bx;
+    g.ty = by;
+    g.tz = bz;
+    g.ncx = g.L[0] / bx;
+    g.ncy = g.L[1] / by;
+    g.ncz = g.L[2] / bz;
+    g.bvol = bx * by * bz;
 }
 
 // ------------------------------------------------------------------ launchers

@@ -40,14 +40,33 @@ static int check(int Lx, int Ly, int Lz, int Lt) {
             }
             for (int s = 0; s < g.V; ++s)
                 if (seen[s] != 1) ++fails;
-            // reduction partials: room for every reducing launch shape
+            // reduction partials: room for every reducing launch shape (a
+            // launch writes index block * nrhs + rhs for each of its blocks
+            // per rhs)
             for (int nrhs = 1; nrhs <= 12; ++nrhs) {
                 const long long cap = wd::reduce_partials_cap(g, nrhs);
-                const int bs = wd::block_for_nrhs(nrhs);
-                if ((long long)wd::blocks_for((long long)g.V * nrhs, bs) * nrhs > cap) ++fails;
-                if (wd::tm_eligible(g, nrhs))
-                    for (int ch = 1; ch <= Lt; ++ch)
-                        if (wd::tm_blocks(g, ch) > cap) ++fails;
+                if ((long long)wd::site_blocks(g.V) * nrhs > cap) ++fails;
+                if (wd::tm_eligible(g)) {
+                    for (int prec = 0; prec < 3; ++prec) {
+                        const int w = wd::tm_wvol(g, prec);
+                        if (w % 64 || g.bvol % w || w > wd::kTmMaxBlock) ++fails;
+                        if ((long long)(g.V / w) * nrhs > cap) ++fails;
+                    }
+                    // chunks tile the time extent
+                    for (int env = 0; env <= Lt + 1; ++env) {
+                        const int ch = wd::tm_chunk_len(g, nrhs, env);
+                        if (ch < 1 || ch > Lt) ++fails;
+                        if ((long long)wd::tm_blocks(g, ch) * ch < (long long)(g.V / g.bvol)) ++fails;
+                    }
+                }
+                // the last entry of the last rhs lies inside the field
+                for (int prec = 0; prec < 3; ++prec) {
+                    const size_t tb = wd::spinor_tile_bytes(prec);
+                    const size_t rhs_bytes = (size_t)(wd::rhs_stride(g.V) / 64) * tb;
+                    const size_t last = (size_t)(nrhs - 1) * rhs_bytes + (size_t)((g.V - 1) / 64) * tb + tb;
+                    if (last > wd::field_data_bytes(prec, g.V, nrhs)) ++fails;
+                    if (wd::rhs_stride(g.V) % 64 || wd::rhs_stride(g.V) < g.V) ++fails;
+                }
             }
         }
       }
@@ -56,8 +75,28 @@ static int check(int Lx, int Ly, int Lz, int Lt) {
     return fails;
 }
 
+// the default brick choice divides the lattice and gives whole tiles
+static int check_choice(int Lx, int Ly, int Lz, int Lt) {
+    wd::Geom g{};
+    g.L[0] = Lx; g.L[1] = Ly; g.L[2] = Lz; g.L[3] = Lt;
+    g.V = Lx * Ly * Lz * Lt;
+    wd::choose_bricks(g);
+    int fails = 0;
+    if (Lx % g.tx || Ly % g.ty || Lz % g.tz || g.bvol != g.tx * g.ty * g.tz) ++fails;
+    if (g.ncx * g.tx != Lx || g.ncy * g.ty != Ly || g.ncz * g.tz != Lz) ++fails;
+    printf("bricks %dx%dx%dx%d: %dx%dx%d\n", Lx, Ly, Lz, Lt, g.tx, g.ty, g.tz);
+    return fails;
+}
+
 int main() {
     int f = 0;
+    f += check_choice(48, 48, 48, 96);
+    f += check_choice(24, 24, 24, 48);
+    f += check_choice(16, 16, 16, 32);
+    f += check_choice(12, 12, 12, 12);
+    f += check_choice(8, 8, 8, 8);
+    f += check_choice(4, 4, 4, 4);
+    f += check_choice(2, 4, 2, 6);
     f += check(2, 2, 2, 2);
     f += check(4, 4, 4, 4);
     f += check(4, 6, 8, 10);
