@@ -9,9 +9,11 @@ throughput: stencil applications x V x 1320 flop over the step wall time.
 The JSON line also carries the time to solution of each solver, the FP64
 stencil's roofline (HIP events recorded on its launch stream, traffic from
 the committed counter summary when it matches the current kernel source),
-the stencil alone per precision, the 12-source batched solve on 24^3 x 48,
-a Poisson request stream through the solve server, and the CPU oracle's
-stencil throughput.  Inputs are synthetic and resident in HBM before timing.
+the stencil alone per precision, a device copy as the practical streaming
+ceiling, the 4^4 and 16^3 x 32 configurations, the 12-source batched solve
+on 24^3 x 48, Poisson request streams through the solve server, and the CPU
+oracle's stencil throughput (and its 4^4 CG time).  Inputs are synthetic and
+resident in HBM before timing.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
     python bench.py --probe                  # workload for rocprofv3 counter runs
@@ -59,7 +61,7 @@ def parse():
     ap.add_argument("--mixed", default="f16", choices=["f32", "f16"])
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--probe", action="store_true")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="STATS_CSV")
@@ -127,6 +129,7 @@ def main():
     kappa = args.kappa
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
+    copy_gbs = copy_bandwidth(torch)
 
     t0 = time.time()
     Uh = torch.empty((V, 4, 3, 3, 2), dtype=torch.float64, pin_memory=True)
@@ -232,6 +235,8 @@ def main():
             "launches": apps["f64"],
             "bytes_per_site": BYTES_PER_SITE["f64"],
             "sites_per_launch": V,
+            "copy_GBps": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
     }
     if cntl:
@@ -248,6 +253,7 @@ def main():
         lat.close()
         del Ud
         torch.cuda.empty_cache()
+        ex["small_configs"] = small_configs(np, torch, synth, wd)
         ex["multi_rhs"] = multi_rhs(np, torch, synth, wd)
         ex["serving"] = serving(np, torch, synth, wd, args.serve_requests)
         out["extras"] = ex
@@ -256,6 +262,85 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(np)
     print(json.dumps(out))
+
+
+def copy_bandwidth(torch):
+    """Device-to-device copy of 2 GiB (read + write bytes over time, median
+    of 5): the practical streaming ceiling next to the 8 TB/s peak."""
+    n = 256 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    ts = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    gbs = 2 * n * 8 / statistics.median(ts) / 1e6
+    log(f"copy: {gbs:.0f} GB/s")
+    return gbs
+
+
+def small_configs(np, torch, synth, wd):
+    """The 4^4 configuration (Haar links seed 1, kappa 0.12, point source)
+    and 16^3 x 32 (eps = 0.3 links seed 2, kappa 0.124, Gaussian source seed
+    102): FP64 and mixed time to a 1e-10 true residual (median of 5 on 4^4,
+    of 3 on 16^3 x 32) and, on 16^3 x 32, the stencil per precision (its
+    fields fit in the 256 MB Infinity Cache: an L2-miss rate, not HBM)."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, dims, seed, kind, kappa, src, reps in (
+            ("4x4x4x4", (4, 4, 4, 4), 1, synth.HAAR, 0.12, "point", 5),
+            ("16x16x16x32", (16, 16, 16, 32), 2, synth.EXP, 0.124, "gauss", 3)):
+        V = int(np.prod(dims))
+        lat = wd.Lattice(dims)
+        lat.set_gauge(torch.from_numpy(synth.gauge(dims, seed, kind, 0.3)).to(dev))
+        b = synth.point_source(dims) if src == "point" else synth.gaussian_spinor(dims, 102)
+        bd = torch.from_numpy(b).to(dev)
+        x = torch.zeros_like(bd)
+        r = {}
+        for prec in ("f64", "f32", "f16"):
+            lat.solve(bd, x, kappa, tol=1e-10, prec=prec)  # warm
+            ts, info = [], None
+            for _ in range(reps):
+                x.zero_()
+                torch.cuda.synchronize()
+                t = time.time()
+                rc, info = lat.solve(bd, x, kappa, tol=1e-10, prec=prec)
+                ts.append(time.time() - t)
+            r[f"cg_{prec}_s"] = round(statistics.median(ts), 5)
+            r[f"cg_{prec}_iters"] = info[0]["iters"]
+            r[f"cg_{prec}_true_rel_resid"] = info[0]["true_rel_resid"]
+        if V >= 1 << 17:
+            for prec in ("f64", "f32", "f16"):
+                fa, fb = wd.Field(lat, prec), wd.Field(lat, prec)
+                fa.load(bd)
+                for _ in range(3):
+                    wd.wd_dslash(lat, kappa, 0, fa, fb)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(20):
+                    wd.wd_dslash(lat, kappa, 0, fa, fb)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 20
+                r[f"dslash_{prec}_ms"] = round(ms, 4)
+                r[f"dslash_{prec}_GFLOPs"] = round(V * FLOP_PER_SITE / ms / 1e6, 1)
+                r[f"dslash_{prec}_GBps_l2_miss"] = round(V * BYTES_PER_SITE[prec] / ms / 1e6, 1)
+                fa.close()
+                fb.close()
+        lat.close()
+        res[name] = r
+    log(f"small configs: {res}")
+    return res
 
 
 def stencil_alone(wd, torch, lat, bd, V, kappa, stream):
@@ -359,7 +444,8 @@ def serving(np, torch, synth, wd, n_requests):
     {8^4, 12^4, 16^3x32, 24^3x48} (two eps = 0.3 gauge fields each), kappa
     uniform in [0.115, 0.1245], 1-12 sources, tol 1e-10, mixed FP32-12;
     64 GiB budget.  The arrival rate is 0.7 x the closed-loop rate measured
-    first with 16 requests submitted at once."""
+    first with 16 requests submitted at once; shorter streams at 0.4x and
+    1.0x sweep the rate."""
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(5)
     sizes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (24, 24, 24, 48)]
@@ -403,23 +489,29 @@ def serving(np, torch, synth, wd, n_requests):
     d0 = run(srv, closed, [0.0] * 16)
     rate = 16 / (time.time() - t)
     srv.close()
-    lam = 0.7 * rate
-    reqs = [draw() for _ in range(n_requests)]
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
-    srv = wd.Server(budget, max_active=8)
-    d1 = run(srv, reqs, arrivals)
-    st = srv.stats()
-    peak = srv.peak_bytes()
-    srv.close()
-    ok = sum(1 for rc, _ in d1.values() if rc == 0)
-    worst = max(max(i["true_rel_resid"] for i in info) for rc, info in d1.values())
+
+    def stream_at(factor, n):
+        lam = factor * rate
+        reqs = [draw() for _ in range(n)]
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
+        srv = wd.Server(budget, max_active=8)
+        d = run(srv, reqs, arrivals)
+        st = srv.stats()
+        peak = srv.peak_bytes()
+        srv.close()
+        ok = sum(1 for rc, _ in d.values() if rc == 0)
+        worst = max(max(i["true_rel_resid"] for i in info) for rc, info in d.values())
+        return {"requests": n, "arrival_rate_per_s": round(lam, 2),
+                "solves_per_s": round(st["solves_per_s"], 2),
+                "p50_latency_s": round(st["p50_s"], 4), "p99_latency_s": round(st["p99_s"], 4),
+                "succeeded": ok, "max_true_rel_resid": worst, "peak_bytes": peak}
+
+    res = stream_at(0.7, n_requests)
+    res.update({"closed_loop_solves_per_s": round(rate, 2), "budget_bytes": budget,
+                "closed_loop_ok": sum(1 for rc, _ in d0.values() if rc == 0)})
+    res["rate_sweep"] = {f"{f}x": stream_at(f, max(16, n_requests // 4)) for f in (0.4, 1.0)}
     for lat in lats:
         lat.close()
-    res = {"requests": n_requests, "closed_loop_solves_per_s": round(rate, 2),
-           "arrival_rate_per_s": round(lam, 2), "solves_per_s": round(st["solves_per_s"], 2),
-           "p50_latency_s": round(st["p50_s"], 4), "p99_latency_s": round(st["p99_s"], 4),
-           "succeeded": ok, "max_true_rel_resid": worst, "peak_bytes": peak,
-           "budget_bytes": budget, "closed_loop_ok": sum(1 for rc, _ in d0.values() if rc == 0)}
     log(f"serving: {res}")
     return res
 
@@ -438,11 +530,21 @@ def cpu_baseline(np):
         wilson.apply_D(U, psi, dims, 0.124)
         ts.append(time.time() - t)
     t = statistics.median(ts)
+    # time to solution of the oracle's CG on the 4^4 configuration
+    from oracle import cg
+    d4 = (4, 4, 4, 4)
+    U4 = synth.gauge(d4, 1, synth.HAAR, 0.3)
+    b4 = synth.point_source(d4)
+    tc = time.time()
+    _, it4, _ = cg.cgnr(lambda v: wilson.apply_D(U4, v, d4, 0.12),
+                        lambda v: wilson.apply_Ddag(U4, v, d4, 0.12), b4, tol=1e-10)
+    tc = time.time() - tc
     return {"value": round(V * FLOP_PER_SITE / t / 1e9, 3), "unit": "GFLOP/s",
             "cores": 1, "kind": "oracle",
             "sample": f"oracle apply_D (NumPy einsum stencil, complex128) on 16^3x32, median of 3 "
                       f"runs of {t:.2f}s; 1 thread used (einsum is single-threaded), "
-                      f"{os.cpu_count()} cores present"}
+                      f"{os.cpu_count()} cores present",
+            "cg_4x4x4x4_s": round(tc, 4), "cg_4x4x4x4_iters": it4}
 
 
 # ------------------------------------------------------------------ profiling helpers

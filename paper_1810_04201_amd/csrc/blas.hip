@@ -14,29 +14,31 @@ static constexpr int kBS = 256;  // gauge kernels (one lane per site)
 
 // One block: fixed-order sum of nb partials per rhs, then the finaliser.
 // The order for an rhs does not depend on nrhs (thread t sums partials
-// t, t + 256, ...; a butterfly inside each wave; the four waves in order),
-// so a batched solve reproduces the single-rhs solves bit for bit.
+// t + 4jT, t + (4j+1)T, t + (4j+2)T, t + (4j+3)T into four running sums,
+// T = 1024; a butterfly inside each wave; the 16 waves in order), so a
+// batched solve reproduces the single-rhs solves bit for bit.
 // gated: skip when no rhs is iterating (the producing kernel returned early
 // and wrote no partials).
-constexpr int kFinalizeThreads = 256;
+constexpr int kFinalizeThreads = 1024;
 
 __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(RedArgs red, int nb, int gated) {
     if (gated && red.batch->n_active == 0) return;
-    __shared__ double sm[(kFinalizeThreads / 64) * 12];
+    constexpr int T = kFinalizeThreads, NW = T / 64;
+    __shared__ double sm[NW * 12];
     const int nrhs = red.ctl.nrhs;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double acc[12];
-#pragma unroll
-    for (int r = 0; r < 12; ++r) acc[r] = 0.0;
-    for (int b = tid; b < nb; b += kFinalizeThreads) {
-        const double *p = red.partials + (size_t)b * nrhs;
-#pragma unroll
-        for (int r = 0; r < 12; ++r)
-            if (r < nrhs) acc[r] += p[r];
-    }
-#pragma unroll
-    for (int r = 0; r < 12; ++r) {
-        double v = acc[r];
+    const double *P = red.partials;
+    for (int r = 0; r < nrhs; ++r) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = tid;
+        for (; b + 3 * T < nb; b += 4 * T) {
+            a0 += P[(size_t)b * nrhs + r];
+            a1 += P[(size_t)(b + T) * nrhs + r];
+            a2 += P[(size_t)(b + 2 * T) * nrhs + r];
+            a3 += P[(size_t)(b + 3 * T) * nrhs + r];
+        }
+        for (; b < nb; b += T) a0 += P[(size_t)b * nrhs + r];
+        double v = (a0 + a1) + (a2 + a3);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) sm[w * 12 + r] = v;
@@ -44,7 +46,7 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(RedArgs red, int 
     __syncthreads();
     if (tid < nrhs && red.mode != RED_NONE) {
         double t = 0.0;
-        for (int k = 0; k < kFinalizeThreads / 64; ++k) t += sm[k * 12 + tid];
+        for (int k = 0; k < NW; ++k) t += sm[k * 12 + tid];
         finalize_rhs(red, tid, t);
     }
     __syncthreads();

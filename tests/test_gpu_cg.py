@@ -135,6 +135,22 @@ def test_multi_rhs_column_equals_single_bitwise(env, dims, prec):
         assert info[k]["reliable_updates"] == info1[0]["reliable_updates"]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f16"])
+def test_cg_384_site_bricks(env, monkeypatch, prec):
+    """CG with 8x8x6 bricks (marching parts of 384 or 192 sites, one partial
+    sum per part of a slice): solution against the oracle."""
+    monkeypatch.setenv("WD_BRICK", "8,8,6")
+    dims = (8, 8, 12, 6)
+    print(f"cg 384-site bricks prec={prec}", flush=True)
+    U = gauge(dims, 23)
+    b = synth.gaussian_spinor(dims, 24)
+    rc, info, x = _solve(env, dims, U, b, 0.124, tol=1e-10, prec=prec)
+    assert rc == 0 and info[0]["true_rel_resid"] <= 1e-10
+    xo, it, oinfo = _oracle(dims, U, b, 0.124, 1e-12)
+    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+    assert rel(x, xo) <= max(1e-9, 2e-10 * cond)
+
+
 def test_deterministic_bitwise(env):
     dims = (4, 6, 8, 10)
     U = gauge(dims, 12)
