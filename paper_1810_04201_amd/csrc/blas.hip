@@ -17,12 +17,12 @@ static constexpr int kBS = 256;  // gauge kernels (one lane per site)
 // t + 4jT, t + (4j+1)T, t + (4j+2)T, t + (4j+3)T into four running sums,
 // T = 1024; a butterfly inside each wave; the 16 waves in order), so a
 // batched solve reproduces the single-rhs solves bit for bit.
-// gated: skip when no rhs is iterating (the producing kernel returned early
-// and wrote no partials).
+// gate_mode >= 0: skipped when the producing kernel's batch gate was off
+// (it returned early and wrote no partials).
 constexpr int kFinalizeThreads = 1024;
 
-__global__ void __launch_bounds__(kFinalizeThreads) k_finalize(RedArgs red, int nb, int gated) {
-    if (gated && red.batch->n_active == 0) return;
+__global__ void __launch_bounds__(kFinalizeThreads) k_finalize(RedArgs red, int nb, int gate_mode) {
+    if (gate_mode >= 0 && gate_off(Gate{nullptr, red.batch, gate_mode})) return;
     constexpr int T = kFinalizeThreads, NW = T / 64;
     __shared__ double sm[NW * 12];
     const int nrhs = red.ctl.nrhs;
@@ -53,8 +53,8 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(RedArgs red, int 
     if (tid == 0 && red.mode != RED_NONE) recount_batch(red);
 }
 
-void launch_finalize(const RedArgs &red, int nb, bool gated, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, s, red, nb, gated ? 1 : 0);
+void launch_finalize(const RedArgs &red, int nb, int gate_mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, s, red, nb, gate_mode);
 }
 
 // ------------------------------------------------------------------ gauge
@@ -161,9 +161,9 @@ __global__ void k_export(FieldRef f, double2 *__restrict__ canon, Geom geo) {
 
 template <int SRC, int DST>
 __global__ void k_convert(FieldRef a, FieldRef b, Gate gate) {
-    if (gate.batch && gate.batch->n_active == 0) return;
+    if (gate_off(gate)) return;
     const int r = blockIdx.y;
-    if (gate.st && !gate.st[r].active) return;
+    if (!gate_rhs(gate, r)) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.V) return;
     cx<double> v[12];
@@ -181,11 +181,16 @@ __global__ void k_zero(FieldRef f) {
     store_from_double<PREC>(rhs_view(f, blockIdx.y), i, v);
 }
 
-// x64 += xlo ; xlo = 0 for rhs not yet converged
+// x64 += xlo ; xlo = 0 for the rhs a reliable update takes (GATE_TRIGGER),
+// else for every rhs not yet converged
 template <int PL>
-__global__ void k_accum_zero(FieldRef x, FieldRef xl, const RhsState *st) {
+__global__ void k_accum_zero(FieldRef x, FieldRef xl, Gate gate) {
     const int r = blockIdx.y;
-    if (st[r].converged) return;
+    if (gate.mode == GATE_TRIGGER) {
+        if (gate_off(gate) || !gate_rhs(gate, r)) return;
+    } else if (gate.st[r].converged) {
+        return;
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= x.V) return;
     const FieldRef xv = rhs_view(x, r), lv = rhs_view(xl, r);
@@ -237,9 +242,9 @@ void launch_zero(FieldRef f, hipStream_t s) {
                      hipLaunchKernelGGL(k_zero<PP>, field_grid(f), dim3(kSiteBlock), 0, s, f));
 }
 
-void launch_accum_zero(FieldRef x, FieldRef xl, const RhsState *st, hipStream_t s) {
+void launch_accum_zero(FieldRef x, FieldRef xl, Gate gate, hipStream_t s) {
     WD_DISPATCH_PREC(xl.prec, hipLaunchKernelGGL(k_accum_zero<PP>, field_grid(x),
-                                                 dim3(kSiteBlock), 0, s, x, xl, st));
+                                                 dim3(kSiteBlock), 0, s, x, xl, gate));
 }
 
 // ------------------------------------------------------------------ CG updates
@@ -251,9 +256,9 @@ void launch_accum_zero(FieldRef x, FieldRef xl, const RhsState *st, hipStream_t 
 template <int PX, int PPP>
 __global__ void k_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, RedArgs red,
                             Gate gate) {
-    if (gate.batch->n_active == 0) return;
+    if (gate_off(gate)) return;
     const int rhs = blockIdx.y;
-    if (!gate.st[rhs].active) return;
+    if (!gate_rhs(gate, rhs)) return;
     using R = typename Spinor<PX>::R;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double nrm = 0.0;
@@ -280,10 +285,10 @@ __global__ void k_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, Red
 // p = r + beta p (RESTART: at the first reliable update p = r)
 template <int PX, int PPP, bool RESTART>
 __global__ void k_update_p(FieldRef p, FieldRef r, Gate gate) {
-    if (gate.batch->n_active == 0) return;
+    if (gate_off(gate)) return;
     const int rhs = blockIdx.y;
+    if (!gate_rhs(gate, rhs)) return;
     const RhsState &st = gate.st[rhs];
-    if (!st.active) return;
     using R = typename Spinor<PX>::R;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.V) return;
@@ -316,7 +321,7 @@ void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const Red
         hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F32>), gr, bs, 0, s, x, r, p, Ap, red, gate);
     else
         hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F16>), gr, bs, 0, s, x, r, p, Ap, red, gate);
-    launch_finalize(red, gr.x, true, s);
+    launch_finalize(red, gr.x, GATE_ACTIVE, s);
 }
 
 template <bool RESTART>
@@ -340,9 +345,12 @@ void launch_restart_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s) {
 
 // ------------------------------------------------------------------ residual / norms
 
-// r = b - Ax (Ax absent: r = b), float64; reduce |r|^2
-__global__ void k_residual(FieldRef r, FieldRef b, FieldRef Ax, RedArgs red) {
+// r = b - Ax (Ax absent: r = b), float64; reduce |r|^2.  A gated-off rhs
+// writes no partial (the finaliser ignores it).
+__global__ void k_residual(FieldRef r, FieldRef b, FieldRef Ax, RedArgs red, Gate gate) {
+    if (gate_off(gate)) return;
     const int rhs = blockIdx.y;
+    if (!gate_rhs(gate, rhs)) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double nrm = 0.0;
     if (i < r.V) {
@@ -375,16 +383,17 @@ __global__ void k_norm(FieldRef f, RedArgs red) {
     reduce_block(nrm, red.partials, (size_t)blockIdx.x * f.nrhs + rhs);
 }
 
-void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, hipStream_t s) {
+void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, Gate gate,
+                     hipStream_t s) {
     const dim3 gr = field_grid(r);
-    hipLaunchKernelGGL(k_residual, gr, dim3(kSiteBlock), 0, s, r, b, Ax, red);
-    launch_finalize(red, gr.x, false, s);
+    hipLaunchKernelGGL(k_residual, gr, dim3(kSiteBlock), 0, s, r, b, Ax, red, gate);
+    launch_finalize(red, gr.x, gate.batch ? gate.mode : -1, s);
 }
 
 void launch_norm(FieldRef f, const RedArgs &red, hipStream_t s) {
     const dim3 gr = field_grid(f);
     WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_norm<PP>, gr, dim3(kSiteBlock), 0, s, f, red));
-    launch_finalize(red, gr.x, false, s);
+    launch_finalize(red, gr.x, -1, s);
 }
 
 __global__ void k_init_state(RhsState *st, BatchState *batch, int nrhs) {

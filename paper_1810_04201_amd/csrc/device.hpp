@@ -266,11 +266,28 @@ struct Link<WD_F16> {
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
+// the launch is off for this gate (uniform over the grid)
+__device__ __forceinline__ bool gate_off(const Gate &g) {
+    if (!g.batch) return false;
+    if (g.mode == GATE_TRIGGER) return !(g.batch->n_active == 0 && g.batch->n_trigger > 0);
+    return g.batch->n_active == 0;
+}
+
+// the gate takes right-hand side r (uniform over a workgroup)
+__device__ __forceinline__ bool gate_rhs(const Gate &g, int r) {
+    if (!g.st) return true;
+    const RhsState &s = g.st[r];
+    if (g.mode == GATE_TRIGGER) return s.trigger && !s.converged;
+    if (g.mode == GATE_RESTART) return s.restarted != 0;
+    return s.active != 0;
+}
+
 __device__ inline void finalize_rhs(const RedArgs &red, int r, double total) {
     RhsState &st = red.st[r];
     const SolveCtl &c = red.ctl;
     switch (red.mode) {
         case RED_ALPHA:
+            st.restarted = 0;
             if (st.active) {
                 st.tt = total;
                 if (!(total > 0.0) || !finite(total)) {
@@ -328,11 +345,13 @@ __device__ inline void finalize_rhs(const RedArgs &red, int r, double total) {
                     st.rr_max = total;
                     st.since = 0;
                     st.active = 1;
+                    st.restarted = 1;
                 }
             }
             break;
         case RED_B0:
             st.rr0 = total;
+            st.restarted = 0;
             st.active = 0;
             st.converged = 0;
             st.failed = 0;

@@ -236,15 +236,15 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
                                                 FieldRef out, double kappa_d, RedArgs red,
                                                 Gate gate) {
     using R = typename Spinor<PREC>::R;
-    if (gate.batch && gate.batch->n_active == 0) return;  // grid-uniform
+    if (gate_off(gate)) return;  // grid-uniform
     // logical block = site block * nrhs + rhs: the workgroups of all rhs on
     // the same sites are neighbours in the XCD's run and share its L2 links
     const int nrhs = in.nrhs;
     const int lb = logical_block();
     const int sb = lb / nrhs;
     const int rhs = lb - sb * nrhs;
-    // a frozen rhs: the finaliser ignores its partials
-    if (gate.st && !gate.st[rhs].active) return;  // workgroup-uniform
+    // a gated-off rhs: the finaliser ignores its partials
+    if (!gate_rhs(gate, rhs)) return;  // workgroup-uniform
     const FieldRef fin = rhs_view(in, rhs);
     const int site = sb * blockDim.x + threadIdx.x;
     double nrm = 0.0;
@@ -326,15 +326,15 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
     using R = typename Spinor<PREC>::R;
     extern __shared__ __align__(16) char lds[];
     __shared__ double wsum[kTmMaxBlock / 64];
-    if (gate.batch && gate.batch->n_active == 0) return;  // grid-uniform
+    if (gate_off(gate)) return;  // grid-uniform
     const int nrhs = in.nrhs;
     const int wvol = (int)blockDim.x;  // sites of this workgroup's part of a slice
     const int nsub = g.bvol / wvol;
     const int lb = logical_block();
     const int cb = lb / nrhs;
     const int rhs = lb - cb * nrhs;
-    // a frozen rhs: the finaliser ignores its partials
-    if (gate.st && !gate.st[rhs].active) return;  // workgroup-uniform
+    // a gated-off rhs: the finaliser ignores its partials
+    if (!gate_rhs(gate, rhs)) return;  // workgroup-uniform
     const FieldRef fin = rhs_view(in, rhs), fout = rhs_view(out, rhs);
     const int cc = cb / nsub;
     const int h = cb - cc * nsub;
@@ -520,7 +520,7 @@ static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger
             launch_tm_k<PREC, false, false>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
     }
     // one partial per part of a brick slice: V / wvol of them per rhs
-    if (red) launch_finalize(r, g.V / wvol, gate.batch != nullptr, s);
+    if (red) launch_finalize(r, g.V / wvol, gate.batch ? gate.mode : -1, s);
 }
 
 template <int PREC>
@@ -550,7 +550,7 @@ static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagg
         else
             hipLaunchKernelGGL((k_dslash<PREC, false, false, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
     }
-    if (red) launch_finalize(r, nb, gate.batch != nullptr, s);
+    if (red) launch_finalize(r, nb, gate.batch ? gate.mode : -1, s);
 }
 
 void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,

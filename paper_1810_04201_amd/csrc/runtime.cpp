@@ -276,7 +276,7 @@ int wd_dslash(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_
     hipStream_t s = (hipStream_t)stream;
     void *g = gauge_for(lat, in->prec, s, &err);
     if (!g) return err;
-    dslash(lat, g, kappa, dagger, in->ref, out->ref, nullptr, Gate{nullptr, nullptr}, s);
+    dslash(lat, g, kappa, dagger, in->ref, out->ref, nullptr, Gate{nullptr, nullptr, GATE_ACTIVE}, s);
     WD_LAUNCH_CHECK();
     return WD_OK;
 }
@@ -305,7 +305,7 @@ int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, cons
     cur = (char *)mem + one;
     FieldRef b = carve(cur, prec, nrhs, V);
     launch_import(in, a, lat->g, s);
-    dslash(lat, g, kappa, dagger, a, b, nullptr, Gate{nullptr, nullptr}, s);
+    dslash(lat, g, kappa, dagger, a, b, nullptr, Gate{nullptr, nullptr, GATE_ACTIVE}, s);
     launch_export(b, out, lat->g, s);
     (void)hipFreeAsync(mem, s);
     WD_LAUNCH_CHECK();

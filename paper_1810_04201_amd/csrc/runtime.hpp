@@ -103,14 +103,13 @@ class Solve {
     struct Pending {
         hipEvent_t ev;
         int slot;
-        int epoch;
     };
     void enqueue_inner(int iters);
-    void enqueue_reliable(bool first);
+    void enqueue_reliable();
     void enqueue_finish();
     int push_status();
     RedArgs red(int mode) const;
-    Gate gate() const { return Gate{st_, batch_}; }
+    Gate gate() const { return Gate{st_, batch_, GATE_ACTIVE}; }
 
     wd_lattice *lat_;
     wd_solve_params p_;
@@ -119,6 +118,7 @@ class Solve {
     hipStream_t s_ = nullptr;
     int prec_;
     int chunk_ = 8;
+    int rel_every_ = 1;  // inner iterations between gated reliable updates
     void *gauge64_ = nullptr, *gauge_lo_ = nullptr;
     void *mem_ = nullptr;
     size_t bytes_ = 0;
@@ -137,7 +137,6 @@ class Solve {
     BatchState *h_batch_ = nullptr;  // res_->h_batch
     std::deque<Pending> pending_;
     int next_slot_ = 0;
-    int epoch_ = 0;
     int phase_ = 0;  // 0 running, 1 finishing, 2 done
     hipEvent_t final_ev_ = nullptr;
     int result_ = WD_OK;

@@ -19,6 +19,12 @@
 // residual meets the tolerance.  Plain FP64 CG triggers it only at the
 // convergence estimate; mixed precision also every `reliable_max_iter`
 // iterations and when |r_lo| drops below delta * max |r_lo|.
+//
+// The decision is taken on the device: every few inner iterations the
+// stream carries a reliable update gated on the solver state (it runs only
+// when every unfinished rhs is frozen and one waits for it), so the host only
+// watches for the end of the solve and never sits between a trigger and its
+// update.
 #include <cmath>
 #include <cstring>
 
@@ -155,6 +161,9 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     // iterations per status read: large lattices need few, tiny ones many
     const double site_iters = 4.0e7 / (double)n;
     chunk_ = site_iters < 4 ? 4 : (site_iters > 64 ? 64 : (int)site_iters);
+    // a gated reliable update after every iteration on large lattices (its
+    // launches cost nothing next to an iteration), every 4 on small ones
+    rel_every_ = n >= (1 << 20) ? 1 : 4;
     return WD_OK;
 }
 
@@ -171,7 +180,7 @@ RedArgs Solve::red(int mode) const {
 
 int Solve::start() {
     const double k = p_.kappa;
-    const Gate none{nullptr, nullptr};
+    const Gate none{nullptr, nullptr, GATE_ACTIVE};
     launch_init_state(st_, batch_, p_.nrhs, s_);
     launch_import(b_, b64_, lat_->g, s_);
     RedArgs rb = red(RED_B0);
@@ -181,7 +190,17 @@ int Solve::start() {
     else
         launch_zero(x64_, s_);
     launch_zero(xl_, s_);
-    enqueue_reliable(true);
+    // the first reliable update forms r and p for every rhs with b' != 0
+    if (p_.x0_given) {
+        enqueue_reliable();
+    } else {
+        const Gate trig{st_, batch_, GATE_TRIGGER};
+        const Gate rst{st_, batch_, GATE_RESTART};
+        RedArgs rt = red(RED_TRUE);
+        launch_residual(r64_, bp_, FieldRef{}, rt, trig, s_);  // x = 0: r = b'
+        launch_convert(r64_, rl_, rst, s_);
+        launch_restart_p(pl_, rl_, rst, s_);
+    }
     if (launch_failed()) return fail(WD_ERR_HIP, "kernel launch failed");
     return push_status();
 }
@@ -196,32 +215,33 @@ void Solve::enqueue_inner(int iters) {
         dslash(lat_, gauge_lo_, k, 1, tl_, apl_, nullptr, g, s_);
         launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
         launch_update_p(pl_, rl_, g, s_);
+        if ((i + 1) % rel_every_ == 0 || i + 1 == iters) enqueue_reliable();
     }
 }
 
-void Solve::enqueue_reliable(bool first) {
+// A reliable update gated on the device (GATE_TRIGGER): a no-op unless every
+// unfinished rhs is frozen and at least one waits for it; then it takes the
+// waiting rhs, and resets r_lo and p of those it restarts (GATE_RESTART).
+void Solve::enqueue_reliable() {
     const double k = p_.kappa;
-    const Gate none{nullptr, nullptr};
+    const Gate trig{st_, batch_, GATE_TRIGGER};
+    const Gate rst{st_, batch_, GATE_RESTART};
     RedArgs rt = red(RED_TRUE);
-    if (first && !p_.x0_given) {
-        launch_residual(r64_, bp_, FieldRef{}, rt, s_);  // x = 0: r = b'
-    } else {
-        launch_accum_zero(x64_, xl_, st_, s_);
-        dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, none, s_);
-        dslash(lat_, gauge64_, k, 1, t64_, ax64_, nullptr, none, s_);
-        launch_residual(r64_, bp_, ax64_, rt, s_);
-    }
-    launch_convert(r64_, rl_, gate(), s_);
-    launch_restart_p(pl_, rl_, gate(), s_);
+    launch_accum_zero(x64_, xl_, trig, s_);
+    dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, trig, s_);
+    dslash(lat_, gauge64_, k, 1, t64_, ax64_, nullptr, trig, s_);
+    launch_residual(r64_, bp_, ax64_, rt, trig, s_);
+    launch_convert(r64_, rl_, rst, s_);
+    launch_restart_p(pl_, rl_, rst, s_);
 }
 
 void Solve::enqueue_finish() {
     const double k = p_.kappa;
-    const Gate none{nullptr, nullptr};
-    launch_accum_zero(x64_, xl_, st_, s_);
+    const Gate none{nullptr, nullptr, GATE_ACTIVE};
+    launch_accum_zero(x64_, xl_, Gate{st_, nullptr, GATE_ACTIVE}, s_);  // unconverged rhs
     dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, none, s_);
     RedArgs ra = red(RED_AUX);
-    launch_residual(ax64_, b64_, t64_, ra, s_);  // |b - D x|^2
+    launch_residual(ax64_, b64_, t64_, ra, none, s_);  // |b - D x|^2
     RedArgs rb = red(RED_AUX2);
     launch_norm(b64_, rb, s_);                  // |b|^2
     launch_export(x64_, x_, lat_->g, s_);
@@ -240,7 +260,7 @@ int Solve::push_status() {
             hipSuccess ||
         hipEventRecord(res_->ev[slot], s_) != hipSuccess)
         return fail(WD_ERR_HIP, "status copy failed");
-    pending_.push_back(Pending{res_->ev[slot], slot, epoch_});
+    pending_.push_back(Pending{res_->ev[slot], slot});
     return WD_OK;
 }
 
@@ -276,16 +296,10 @@ int Solve::advance(bool block) {
         if (e != hipSuccess) return fail(WD_ERR_HIP, "solve failed on the device: %s",
                                          hipGetErrorString(e));
         pending_.pop_front();
-        if (f.epoch != epoch_) continue;  // taken before the last reliable update
         const BatchState &bs = h_batch_[f.slot];
-        if (bs.n_active > 0) continue;
-        if (bs.n_trigger > 0) {
-            enqueue_reliable(false);
-            ++epoch_;
-            int rc = push_status();
-            if (rc) return rc;
-            continue;
-        }
+        // still iterating, or frozen rhs that the next gated reliable update
+        // (already in the stream) will take
+        if (bs.n_active > 0 || bs.n_trigger > 0) continue;
         // every rhs converged or failed: pending inner chunks are no-ops
         enqueue_finish();
         if (launch_failed()) return fail(WD_ERR_HIP, "kernel launch failed");

@@ -184,7 +184,8 @@ struct RhsState {
     int iters;       // CG iterations done
     int since;       // iterations since the last reliable update
     int updates;     // reliable updates (true-residual recomputations)
-    int pad;
+    int restarted;   // the last reliable update restarted the recursion (until
+                     // the next inner iteration): r_lo and p are to be reset
 };
 
 struct BatchState {
@@ -194,11 +195,22 @@ struct BatchState {
     int pad;
 };
 
-// Optional gating of a kernel on the solver state: a kernel returns at once
-// when batch->n_active == 0 and skips rhs whose st[rhs].active == 0.
+// Optional gating of a kernel on the solver state, uniform over the launch
+// (batch) and over a workgroup (rhs):
+//   GATE_ACTIVE   inner iterations: off when no rhs is iterating; rhs with
+//                 active != 0.
+//   GATE_TRIGGER  a reliable update: off unless every unfinished rhs is
+//                 frozen and at least one waits for it; rhs with trigger set
+//                 (not converged).
+//   GATE_RESTART  the reset of r_lo and p after a reliable update: rhs the
+//                 update restarted.
+// batch == nullptr: no batch test; st == nullptr: every rhs.
+enum GateMode { GATE_ACTIVE = 0, GATE_TRIGGER = 1, GATE_RESTART = 2 };
+
 struct Gate {
     const RhsState *st;
     const BatchState *batch;
+    int mode;
 };
 
 struct SolveCtl {
@@ -376,8 +388,9 @@ void launch_export(FieldRef f, double *canon, const Geom &g, hipStream_t s);
 // dst = src with a format conversion (same nrhs); gated rhs only
 void launch_convert(FieldRef src, FieldRef dst, Gate gate, hipStream_t s);
 void launch_zero(FieldRef f, hipStream_t s);
-// x64 += xlo ; xlo = 0 for every rhs that has not converged
-void launch_accum_zero(FieldRef x64, FieldRef xlo, const RhsState *st, hipStream_t s);
+// x64 += xlo ; xlo = 0: gate.mode GATE_TRIGGER for the rhs a reliable update
+// takes (with its batch test), otherwise every rhs that has not converged
+void launch_accum_zero(FieldRef x64, FieldRef xlo, Gate gate, hipStream_t s);
 
 // out = D in (dagger 0) or D^dag in (dagger 1); red != nullptr fuses the
 // reduction of |out|^2 with red->mode
@@ -390,16 +403,18 @@ void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const Red
 // p = r + beta p for active rhs
 void launch_update_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s);
 // r = b - Ax (Ax.data == nullptr: r = b) in float64, reduce |r|^2 with red.mode
-void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, hipStream_t s);
+void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, Gate gate,
+                     hipStream_t s);
 // reduce |f|^2 (any precision) with red.mode
 void launch_norm(FieldRef f, const RedArgs &red, hipStream_t s);
 // phase 2 of a reduction: one block sums the nb per-block partials in a fixed
-// order and runs the finaliser (gated: skip when no rhs is iterating)
-void launch_finalize(const RedArgs &red, int nb, bool gated, hipStream_t s);
+// order and runs the finaliser; gate_mode >= 0: skipped when the producing
+// kernel's batch gate (GateMode) was off, -1: always runs
+void launch_finalize(const RedArgs &red, int nb, int gate_mode, hipStream_t s);
 // zero the states and the batch counters
 void launch_init_state(RhsState *st, BatchState *batch, int nrhs, hipStream_t s);
-// after a reliable update, for the rhs it restarted (active): p = r at the
-// first update, p = r + beta p afterwards
+// after a reliable update, for the rhs it restarted (gate GATE_RESTART):
+// p = r at the first update, p = r + beta p afterwards
 void launch_restart_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s);
 
 }  // namespace wd
