@@ -2,8 +2,9 @@
 
 D is not Hermitian, but gamma_5 D gamma_5 = D^dag (Sec. 2.2), so CG runs on a
 Hermitian positive-definite normal operator.  The paper's listing solves
-D D^dag y = eta and sets psi = D^dag y; this project solves the other normal
-form, D^dag D x = D^dag b (CGNR).  Both reach the unique x = D^{-1} b.
+D D^dag y = eta and sets psi = D^dag y (CGNE, ``cgne``); the default here is
+the other normal form, D^dag D x = D^dag b (CGNR, ``cgnr``).  Both reach the
+unique x = D^{-1} b.
 
 Readings of the printed listing:
 * |.| in the step lengths is the squared 2-norm, so for CGNR
@@ -66,6 +67,48 @@ def cgnr(matvec, matvec_dag, b: np.ndarray, tol: float = 1e-10, max_iter: int = 
     info = {
         "rel_resid": float(np.sqrt(rr / bnorm2)) if bnorm2 > 0 else 0.0,
         "history": hist,
+        "alphas": alphas,
+        "betas": betas,
+        "converged": rr <= target,
+        "bnorm2": bnorm2,
+    }
+    return x, it, info
+
+
+def cgne(matvec, matvec_dag, b: np.ndarray, tol: float = 1e-10, max_iter: int = 20000):
+    """Return (x, iterations, info) for the paper's form of Sec. 2.2: CG on
+    D D^dag y = b, then x = D^dag y.
+
+    Step lengths as read for CGNR, with the roles of D and D^dag exchanged:
+    alpha = ||r||^2 / ||D^dag p||^2, r -= alpha D (D^dag p), beta =
+    ||r_new||^2 / ||r_old||^2.  r is the residual of D x = b itself, so the
+    stop is ||b - D x|| <= tol * ||b||.  Starts from y = 0.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    bnorm2 = _dot_re(b, b)
+    y = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = bnorm2
+    alphas, betas = [], []
+    it = 0
+    target = (tol ** 2) * bnorm2
+    while rr > target and it < max_iter:
+        t = matvec_dag(p)
+        tt = _dot_re(t, t)  # <p, D D^dag p> = ||D^dag p||^2
+        alpha = rr / tt
+        y = y + alpha * p
+        r = r - alpha * matvec(t)
+        rr_new = _dot_re(r, r)
+        beta = rr_new / rr
+        p = r + beta * p
+        rr = rr_new
+        it += 1
+        alphas.append(alpha)
+        betas.append(beta)
+    x = matvec_dag(y)
+    info = {
+        "rel_resid": float(np.sqrt(rr / bnorm2)) if bnorm2 > 0 else 0.0,
         "alphas": alphas,
         "betas": betas,
         "converged": rr <= target,

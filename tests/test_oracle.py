@@ -287,6 +287,42 @@ def test_cg_config1_4x4_vs_lapack():
     assert rel(D(x), b) < 1e-8
 
 
+@pytest.mark.parametrize("dims,seed,kappa", [((2, 2, 2, 2), 1, 0.12), ((2, 2, 2, 4), 3, 0.124)])
+def test_cgne_vs_lapack_tiny(dims, seed, kappa):
+    """The paper's form (CG on D D^dag y = b, x = D^dag y) reaches the dense
+    solution, with the true residual of D x = b at the tolerance."""
+    U = synth.gauge(dims, seed, synth.HAAR)
+    b = synth.gaussian_spinor(dims, seed + 40)
+    D = lambda v: wilson.apply_D(U, v, dims, kappa)  # noqa: E731
+    Dd = lambda v: wilson.apply_Ddag(U, v, dims, kappa)  # noqa: E731
+    x, it, info = cg.cgne(D, Dd, b, tol=1e-13)
+    want = _solve_dense(U, dims, kappa, b)
+    assert info["converged"] and rel(x, want) < 1e-12
+    assert rel(D(x), b) <= 1e-12
+
+
+def test_cgne_config1_and_paper_sign():
+    """4^4 configuration: CGNE and CGNR agree; with the paper's +kappa sign
+    the solution is eps x_- (D_+ = eps D_- eps, even extents)."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge(dims, 1, synth.HAAR)
+    b = synth.point_source(dims, 0, 0, 0)
+    k = 0.12
+    D = lambda v: wilson.apply_D(U, v, dims, k)  # noqa: E731
+    Dd = lambda v: wilson.apply_Ddag(U, v, dims, k)  # noqa: E731
+    xe, ite, _ = cg.cgne(D, Dd, b, tol=1e-11)
+    xr, itr, _ = cg.cgnr(D, Dd, b, tol=1e-11)
+    assert rel(xe, xr) < 1e-9 and rel(xe, _solve_dense(U, dims, k, b)) < 1e-9
+    Dp = lambda v: wilson.apply_D(U, v, dims, k, hop_sign=+1)  # noqa: E731
+    Dpd = lambda v: wilson.apply_Ddag(U, v, dims, k, hop_sign=+1)  # noqa: E731
+    xp, itp, _ = cg.cgne(Dp, Dpd, b, tol=1e-11)
+    V = int(np.prod(dims))
+    eps = np.array([(-1) ** sum(wilson.coords(s, dims)) for s in range(V)],
+                   dtype=np.float64)[:, None, None, None]
+    assert rel(xp, eps * cg.cgne(D, Dd, eps * b, tol=1e-11)[0]) < 1e-9
+    assert abs(itp - ite) <= 1
+
+
 def test_cg_warm_start_from_solution():
     dims = (2, 2, 2, 4)
     U = synth.gauge(dims, 5, synth.HAAR)

@@ -94,3 +94,11 @@ def test_cg_wrong_step_length_caught(monkeypatch):
     monkeypatch.setattr(ocg, "_dot_re", bad_dot)
     with pytest.raises(AssertionError):
         T.test_cg_vs_lapack_tiny((2, 2, 2, 2), 1, 0.12)
+
+
+def test_cgne_swapped_operators_caught(monkeypatch):
+    # CG on D^dag D y = b with x = D y (operators exchanged) must fail the pin
+    real = ocg.cgne
+    monkeypatch.setattr(ocg, "cgne", lambda mv, mvd, b, **kw: real(mvd, mv, b, **kw))
+    with pytest.raises(AssertionError):
+        T.test_cgne_vs_lapack_tiny((2, 2, 2, 4), 3, 0.124)
