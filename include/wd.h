@@ -72,12 +72,24 @@ enum {
 
 enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 };
 
-enum { WD_BC_ANTIPERIODIC_T = 1u << 0 };
+/* Lattice flags.  WD_SIGN_PLUS_KAPPA selects the hopping sign as printed in
+ * Eq. (1), D = 1 + kappa * (hops); the default is D = 1 - kappa * (hops).
+ * On even lattices the two are related by D_+ = eps D_- eps with
+ * eps(x) = (-1)^(x+y+z+t): same spectrum, solutions differ by eps. */
+enum { WD_BC_ANTIPERIODIC_T = 1u << 0, WD_SIGN_PLUS_KAPPA = 1u << 1 };
+
+/* Normal-equation forms of the CG solve (Sec. 2.2). */
+enum {
+    WD_FORM_CGNR = 0, /* D^dag D x = D^dag b */
+    WD_FORM_CGNE = 1  /* the paper's listing: D D^dag y = b, x = D^dag y */
+};
 
 /* ---------------------------------------------------------------- lattice */
 
 /* Create a lattice of extents dims (each even, >= 2).  bc_flags:
- * WD_BC_ANTIPERIODIC_T for antiperiodic t (else periodic everywhere).
+ * WD_BC_ANTIPERIODIC_T for antiperiodic t (else periodic everywhere), and
+ * WD_SIGN_PLUS_KAPPA for the +kappa hopping sign on every operator of this
+ * lattice.
  * *out receives an opaque handle owned by the caller; free it with
  * wd_destroy_lattice.  Allocates no device memory yet. */
 int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out);
@@ -142,27 +154,34 @@ int wd_dslash(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_
 
 typedef struct {
     double kappa;              /* hopping parameter */
-    double tol;                /* stop when ||r|| <= tol * ||D^dag b|| (normal equations) */
+    double tol;                /* stop when ||r|| <= tol * ||D^dag b|| (CGNR) or
+                                  ||b - D x|| <= tol * ||b|| (CGNE) */
     int32_t max_iter;          /* cap on CG iterations (inner iterations for mixed) */
     int32_t prec_inner;        /* WD_F64: plain FP64 CG; WD_F32 / WD_F16: mixed precision */
     int32_t nrhs;              /* 1..12 independent right-hand sides */
     int32_t reliable_max_iter; /* mixed: FP64 reliable update at least this often (<= 0: 50) */
     double reliable_delta;     /* mixed: update when ||r_lo|| < delta * max||r_lo|| (<= 0: 0.1) */
-    int32_t x0_given;          /* 1: x holds a starting guess on entry; 0: start from x = 0 */
+    int32_t x0_given;          /* 1: x holds a starting guess on entry; 0: start from x = 0
+                                  (CGNR only: CGNE always starts from y = 0) */
+    int32_t form;              /* WD_FORM_CGNR (0) or WD_FORM_CGNE (1) */
 } wd_solve_params;
 
 typedef struct {
     int32_t status;           /* WD_OK, WD_ERR_NOCONV or WD_ERR_NUMERIC for this rhs */
     int32_t iters;            /* CG iterations (inner iterations for mixed) */
     int32_t reliable_updates; /* FP64 true-residual recomputations (incl. the final check) */
-    double true_rel_resid;    /* ||D^dag b - D^dag D x|| / ||D^dag b|| in FP64 */
+    double true_rel_resid;    /* FP64: ||D^dag b - D^dag D x|| / ||D^dag b|| (CGNR),
+                                 ||b - D D^dag y|| / ||b|| (CGNE) */
     double rel_resid_D;       /* ||b - D x|| / ||b|| in FP64 */
     double seconds;           /* wall time of the solve (submit to completion when served) */
     double queued_seconds;    /* served: submission to admission; 0 for wd_cg_solve */
 } wd_solve_info;
 
-/* Solve D^dag D x = D^dag b for nrhs right-hand sides (blocking; returns when
- * x is written).  b, x: canonical float64 device spinors [nrhs][V][24].
+/* Solve D x = b by CG on the normal equations (Sec. 2.2) for nrhs
+ * right-hand sides (blocking; returns when x is written): D^dag D x = D^dag b
+ * (form WD_FORM_CGNR) or, as in the paper's listing, D D^dag y = b with
+ * x = D^dag y (WD_FORM_CGNE).  b, x: canonical float64 device spinors
+ * [nrhs][V][24].
  * info: host array of nrhs entries.  Returns WD_OK if every rhs converged,
  * else the first failing rhs's status; x always holds the last iterate.
  * Mixed precision (prec_inner = WD_F32/WD_F16) runs the inner CG in that

@@ -38,6 +38,10 @@ WD_ERR_NOTFOUND = -7
 WD_ERR_STATE = -8
 WD_F64, WD_F32, WD_F16 = 0, 1, 2
 WD_BC_ANTIPERIODIC_T = 1
+WD_SIGN_PLUS_KAPPA = 2
+WD_FORM_CGNR, WD_FORM_CGNE = 0, 1
+FORM = {"cgnr": WD_FORM_CGNR, "cgne": WD_FORM_CGNE, WD_FORM_CGNR: WD_FORM_CGNR,
+        WD_FORM_CGNE: WD_FORM_CGNE}
 
 PREC = {"f64": WD_F64, "f32": WD_F32, "f16": WD_F16, WD_F64: WD_F64, WD_F32: WD_F32,
         WD_F16: WD_F16}
@@ -53,7 +57,8 @@ class wd_solve_params(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("prec_inner", ctypes.c_int32),
                 ("nrhs", ctypes.c_int32), ("reliable_max_iter", ctypes.c_int32),
-                ("reliable_delta", ctypes.c_double), ("x0_given", ctypes.c_int32)]
+                ("reliable_delta", ctypes.c_double), ("x0_given", ctypes.c_int32),
+                ("form", ctypes.c_int32)]
 
 
 class wd_solve_info(ctypes.Structure):
@@ -175,11 +180,11 @@ def _dptr(t, numel=None, name="tensor"):
 
 # ------------------------------------------------------------------ C names
 
-def wd_create_lattice(dims, antiperiodic_t: bool = True):
+def wd_create_lattice(dims, antiperiodic_t: bool = True, plus_kappa: bool = False):
     d = (ctypes.c_int32 * 4)(*[int(v) for v in dims])
     h = _vp()
-    _check(lib.wd_create_lattice(d, WD_BC_ANTIPERIODIC_T if antiperiodic_t else 0,
-                                 ctypes.byref(h)))
+    flags = (WD_BC_ANTIPERIODIC_T if antiperiodic_t else 0) | (WD_SIGN_PLUS_KAPPA if plus_kappa else 0)
+    _check(lib.wd_create_lattice(d, flags, ctypes.byref(h)))
     return h
 
 
@@ -208,9 +213,10 @@ def wd_apply_Ddag(h, kappa, prec, inp, out, volume, stream=None):
 
 
 def make_params(kappa, tol=1e-10, max_iter=20000, prec="f64", nrhs=1, reliable_max_iter=50,
-                reliable_delta=0.1, x0_given=False):
+                reliable_delta=0.1, x0_given=False, form="cgnr"):
     return wd_solve_params(float(kappa), float(tol), int(max_iter), PREC[prec], int(nrhs),
-                           int(reliable_max_iter), float(reliable_delta), 1 if x0_given else 0)
+                           int(reliable_max_iter), float(reliable_delta), 1 if x0_given else 0,
+                           FORM[form] if form in FORM else int(form))
 
 
 def wd_cg_solve(h, params: wd_solve_params, b, x, volume, stream=None):
@@ -244,10 +250,10 @@ def wd_timing_read(name: str):
 class Lattice:
     """Owns a wd_lattice handle: geometry plus resident packed gauge forms."""
 
-    def __init__(self, dims, antiperiodic_t: bool = True):
+    def __init__(self, dims, antiperiodic_t: bool = True, plus_kappa: bool = False):
         self.dims = tuple(int(v) for v in dims)
         self.volume = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
-        self.handle = wd_create_lattice(self.dims, antiperiodic_t)
+        self.handle = wd_create_lattice(self.dims, antiperiodic_t, plus_kappa)
 
     def set_gauge(self, U, stream=None):
         wd_set_gauge(self.handle, U, self.volume, stream)
@@ -261,9 +267,10 @@ class Lattice:
         wd_apply(self.handle, kappa, prec, dagger, nrhs, inp, out, self.volume, stream)
 
     def solve(self, b, x, kappa, tol=1e-10, prec="f64", nrhs=1, max_iter=20000,
-              reliable_max_iter=50, reliable_delta=0.1, x0_given=False, stream=None):
+              reliable_max_iter=50, reliable_delta=0.1, x0_given=False, form="cgnr",
+              stream=None):
         p = make_params(kappa, tol, max_iter, prec, nrhs, reliable_max_iter, reliable_delta,
-                        x0_given)
+                        x0_given, form)
         return wd_cg_solve(self.handle, p, b, x, self.volume, stream)
 
     def close(self):
@@ -325,8 +332,9 @@ class Server:
         self._keep = {}
 
     def submit(self, lattice: Lattice, b, x, kappa, tol=1e-10, prec="f32", nrhs=1,
-               max_iter=20000, reliable_max_iter=50, reliable_delta=0.1) -> int:
-        p = make_params(kappa, tol, max_iter, prec, nrhs, reliable_max_iter, reliable_delta)
+               max_iter=20000, reliable_max_iter=50, reliable_delta=0.1, form="cgnr") -> int:
+        p = make_params(kappa, tol, max_iter, prec, nrhs, reliable_max_iter, reliable_delta,
+                        form=form)
         n = lattice.volume * 24 * nrhs
         # the server reads b on its own stream: make the caller's writes visible
         _torch().cuda.current_stream().synchronize()

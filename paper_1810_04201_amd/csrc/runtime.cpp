@@ -120,6 +120,8 @@ static void drain_pending_locked() {
 
 void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
             const FieldRef &out, const RedArgs *red, Gate gate, hipStream_t s) {
+    // the kernels compute in - kappa' * (hops): the +kappa sign is kappa' = -kappa
+    kappa = -lat->hop_sign * kappa;
     if (!g_timing.load(std::memory_order_relaxed)) {
         launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s);
         return;
@@ -161,13 +163,14 @@ int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out
     if (V * 12 * 12 >= (int64_t)1 << 31)
         return fail(WD_ERR_ARG, "volume %lld too large (V * 12 rhs * 12 must be < 2^31)",
                     (long long)V);
-    if (bc_flags & ~(uint32_t)WD_BC_ANTIPERIODIC_T)
-        return fail(WD_ERR_ARG, "unknown boundary flags 0x%x", bc_flags);
+    if (bc_flags & ~(uint32_t)(WD_BC_ANTIPERIODIC_T | WD_SIGN_PLUS_KAPPA))
+        return fail(WD_ERR_ARG, "unknown lattice flags 0x%x", bc_flags);
     wd_lattice *lat = new (std::nothrow) wd_lattice();
     if (!lat) return fail(WD_ERR_NOMEM, "host allocation failed");
     for (int m = 0; m < 4; ++m) lat->g.L[m] = dims[m];
     lat->g.V = (int)V;
     lat->g.antiperiodic = (bc_flags & WD_BC_ANTIPERIODIC_T) ? 1 : 0;
+    lat->hop_sign = (bc_flags & WD_SIGN_PLUS_KAPPA) ? 1.0 : -1.0;
     choose_bricks(lat->g);
     *out = lat;
     return WD_OK;

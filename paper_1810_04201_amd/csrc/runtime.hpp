@@ -16,6 +16,7 @@ struct wd_lattice {
     wd::Geom g{};
     void *gauge[3] = {nullptr, nullptr, nullptr};  // F64-18, F32-12, F16-12
     bool has_gauge = false;
+    double hop_sign = -1.0;  // D = 1 + hop_sign * kappa * (hops); kernels take 1 - kappa' H
     std::mutex mu;
     std::atomic<int> users{0};  // requests in flight on a server
 };
@@ -117,6 +118,7 @@ class Solve {
     double *x_;
     hipStream_t s_ = nullptr;
     int prec_;
+    int d1_ = 0, d2_ = 1;  // daggers of the two stencils of the normal operator
     int chunk_ = 8;
     int rel_every_ = 1;  // inner iterations between gated reliable updates
     void *gauge64_ = nullptr, *gauge_lo_ = nullptr;

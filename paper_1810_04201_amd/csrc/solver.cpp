@@ -1,7 +1,9 @@
 // Conjugate gradient on the normal equations (Sec. 2.2) as a resumable,
 // stream-ordered state machine.
 //
-// Per inner iteration four kernels run back to back on the solve's stream:
+// Per inner iteration four kernels run back to back on the solve's stream
+// (CGNR; the CGNE form of the paper's listing exchanges D and D^dag, solves
+// D D^dag y = b from b' = b and returns x = D^dag y):
 //   t  = D p         (stencil, fused |t|^2 -> alpha = |r|^2 / |t|^2)
 //   Ap = D^dag t     (stencil)
 //   x += alpha p, r -= alpha Ap  (fused |r|^2 -> beta, convergence, triggers)
@@ -33,7 +35,11 @@
 namespace wd {
 
 Solve::Solve(wd_lattice *lat, const wd_solve_params &p, const double *b, double *x)
-    : lat_(lat), p_(p), b_(b), x_(x), prec_(p.prec_inner) {}
+    : lat_(lat), p_(p), b_(b), x_(x), prec_(p.prec_inner) {
+    // the normal operator as two stencils: D^dag D (CGNR) or D D^dag (CGNE)
+    d1_ = p.form == WD_FORM_CGNE ? 1 : 0;
+    d2_ = 1 - d1_;
+}
 
 int SlotRes::create() {
     if (hipHostMalloc((void **)&h_st, sizeof(RhsState) * kSlots * 12) != hipSuccess ||
@@ -70,6 +76,10 @@ int Solve::validate(wd_lattice *lat, const wd_solve_params *p) {
     if (!valid_prec(p->prec_inner)) return fail(WD_ERR_ARG, "unknown precision %d", p->prec_inner);
     if (p->nrhs < 1 || p->nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", p->nrhs);
     if (p->x0_given != 0 && p->x0_given != 1) return fail(WD_ERR_ARG, "x0_given must be 0 or 1");
+    if (p->form != WD_FORM_CGNR && p->form != WD_FORM_CGNE)
+        return fail(WD_ERR_ARG, "unknown form %d", p->form);
+    if (p->form == WD_FORM_CGNE && p->x0_given)
+        return fail(WD_ERR_ARG, "a starting guess needs the CGNR form");
     if (!lat->has_gauge) return fail(WD_ERR_NOGAUGE, "gauge field not set");
     return WD_OK;
 }
@@ -184,7 +194,10 @@ int Solve::start() {
     launch_init_state(st_, batch_, p_.nrhs, s_);
     launch_import(b_, b64_, lat_->g, s_);
     RedArgs rb = red(RED_B0);
-    dslash(lat_, gauge64_, k, 1, b64_, bp_, &rb, none, s_);  // b' = D^dag b, |b'|^2
+    if (p_.form == WD_FORM_CGNE)
+        launch_residual(bp_, b64_, FieldRef{}, rb, none, s_);  // b' = b, |b|^2
+    else
+        dslash(lat_, gauge64_, k, 1, b64_, bp_, &rb, none, s_);  // b' = D^dag b, |b'|^2
     if (p_.x0_given)
         launch_import(x_, x64_, lat_->g, s_);
     else
@@ -211,8 +224,8 @@ void Solve::enqueue_inner(int iters) {
     RedArgs ra = red(RED_ALPHA);
     RedArgs rr = red(RED_RR);
     for (int i = 0; i < iters; ++i) {
-        dslash(lat_, gauge_lo_, k, 0, pl_, tl_, &ra, g, s_);
-        dslash(lat_, gauge_lo_, k, 1, tl_, apl_, nullptr, g, s_);
+        dslash(lat_, gauge_lo_, k, d1_, pl_, tl_, &ra, g, s_);
+        dslash(lat_, gauge_lo_, k, d2_, tl_, apl_, nullptr, g, s_);
         launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
         launch_update_p(pl_, rl_, g, s_);
         if ((i + 1) % rel_every_ == 0 || i + 1 == iters) enqueue_reliable();
@@ -228,8 +241,8 @@ void Solve::enqueue_reliable() {
     const Gate rst{st_, batch_, GATE_RESTART};
     RedArgs rt = red(RED_TRUE);
     launch_accum_zero(x64_, xl_, trig, s_);
-    dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, trig, s_);
-    dslash(lat_, gauge64_, k, 1, t64_, ax64_, nullptr, trig, s_);
+    dslash(lat_, gauge64_, k, d1_, x64_, t64_, nullptr, trig, s_);
+    dslash(lat_, gauge64_, k, d2_, t64_, ax64_, nullptr, trig, s_);
     launch_residual(r64_, bp_, ax64_, rt, trig, s_);
     launch_convert(r64_, rl_, rst, s_);
     launch_restart_p(pl_, rl_, rst, s_);
@@ -239,12 +252,20 @@ void Solve::enqueue_finish() {
     const double k = p_.kappa;
     const Gate none{nullptr, nullptr, GATE_ACTIVE};
     launch_accum_zero(x64_, xl_, Gate{st_, nullptr, GATE_ACTIVE}, s_);  // unconverged rhs
-    dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, none, s_);
     RedArgs ra = red(RED_AUX);
-    launch_residual(ax64_, b64_, t64_, ra, none, s_);  // |b - D x|^2
     RedArgs rb = red(RED_AUX2);
-    launch_norm(b64_, rb, s_);                  // |b|^2
-    launch_export(x64_, x_, lat_->g, s_);
+    if (p_.form == WD_FORM_CGNE) {
+        dslash(lat_, gauge64_, k, 1, x64_, t64_, nullptr, none, s_);  // x = D^dag y
+        dslash(lat_, gauge64_, k, 0, t64_, r64_, nullptr, none, s_);
+        launch_residual(ax64_, b64_, r64_, ra, none, s_);  // |b - D x|^2
+        launch_norm(b64_, rb, s_);                          // |b|^2
+        launch_export(t64_, x_, lat_->g, s_);
+    } else {
+        dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, none, s_);
+        launch_residual(ax64_, b64_, t64_, ra, none, s_);  // |b - D x|^2
+        launch_norm(b64_, rb, s_);                          // |b|^2
+        launch_export(x64_, x_, lat_->g, s_);
+    }
     (void)hipMemcpyAsync(h_st_, st_, sizeof(RhsState) * p_.nrhs, hipMemcpyDeviceToHost, s_);
     (void)hipEventRecord(final_ev_, s_);
 }

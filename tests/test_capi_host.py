@@ -35,6 +35,24 @@ def test_bad_dims_rejected(dims):
     assert not h.value
 
 
+def test_solve_params_layout():
+    # the form field fills the struct's tail padding: every earlier offset
+    # and the size match the header's natural C layout
+    P = wd.wd_solve_params
+    assert ctypes.sizeof(P) == 48
+    assert [getattr(P, f).offset for f in ("kappa", "tol", "max_iter", "prec_inner", "nrhs",
+            "reliable_max_iter", "reliable_delta", "x0_given", "form")] == \
+        [0, 8, 16, 20, 24, 28, 32, 40, 44]
+
+
+def test_plus_kappa_flag_accepted():
+    d = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    h = ctypes.c_void_p()
+    assert wd.lib.wd_create_lattice(d, wd.WD_BC_ANTIPERIODIC_T | wd.WD_SIGN_PLUS_KAPPA,
+                                    ctypes.byref(h)) == wd.WD_OK
+    assert wd.lib.wd_destroy_lattice(h) == wd.WD_OK
+
+
 def test_bad_flags_and_null():
     d = (ctypes.c_int32 * 4)(4, 4, 4, 4)
     h = ctypes.c_void_p()
@@ -62,7 +80,8 @@ def test_solve_rejected_without_gauge_and_bad_params():
                               None) == wd.WD_ERR_NOGAUGE
     for bad in (wd.make_params(0.12, tol=0.0), wd.make_params(0.12, nrhs=13),
                 wd.make_params(0.12, nrhs=0), wd.make_params(float("nan")),
-                wd.make_params(0.12, max_iter=0), wd.make_params(0.12, prec=2)):
+                wd.make_params(0.12, max_iter=0), wd.make_params(0.12, prec=2),
+                wd.make_params(0.12, form=2), wd.make_params(0.12, form="cgne", x0_given=True)):
         if bad.prec_inner == 2:
             bad.prec_inner = 7
         assert wd.lib.wd_cg_solve(lat.handle, ctypes.byref(bad), dummy, ctypes.c_void_p(32),

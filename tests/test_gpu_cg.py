@@ -151,6 +151,50 @@ def test_cg_384_site_bricks(env, monkeypatch, prec):
     assert rel(x, xo) <= max(1e-9, 2e-10 * cond)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_cgne_form_matches_oracle(env, prec):
+    """The paper's form (D D^dag y = b, x = D^dag y): solution against the
+    oracle's CGNE; its true residual is that of D x = b itself."""
+    dims = (4, 6, 8, 10)
+    print(f"cgne prec={prec}", flush=True)
+    U = gauge(dims, 31)
+    b = synth.gaussian_spinor(dims, 32)
+    rc, info, x = _solve(env, dims, U, b, 0.124, tol=1e-10, prec=prec, form="cgne")
+    assert rc == 0, info
+    assert info[0]["true_rel_resid"] <= 1e-10 and info[0]["rel_resid_D"] <= 1.1e-10
+    D = lambda v: wilson.apply_D(U, v, dims, 0.124)  # noqa: E731
+    Dd = lambda v: wilson.apply_Ddag(U, v, dims, 0.124)  # noqa: E731
+    xo, it, oinfo = cg.cgne(D, Dd, b, tol=1e-12)
+    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+    assert rel(x, xo) <= max(1e-9, 2e-10 * cond)
+    if prec == "f64":
+        assert abs(info[0]["iters"] - cg.cgne(D, Dd, b, tol=1e-10)[1]) <= 1
+
+
+def test_plus_kappa_solve_matches_oracle(env):
+    """A lattice with the paper's +kappa sign: the FP64 solve against the
+    oracle's CGNR on D = 1 + kappa (hops)."""
+    torch, dev, wd = env
+    dims = (4, 4, 4, 8)
+    U = gauge(dims, 33)
+    b = synth.gaussian_spinor(dims, 34)
+    lat = wd.Lattice(dims, plus_kappa=True)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    bd = torch.from_numpy(b).to(dev)
+    xd = torch.zeros_like(bd)
+    rc, info = lat.solve(bd, xd, 0.124, tol=1e-10)
+    torch.cuda.synchronize()
+    x = xd.cpu().numpy()
+    lat.close()
+    assert rc == 0
+    D = lambda v: wilson.apply_D(U, v, dims, 0.124, hop_sign=+1)  # noqa: E731
+    Dd = lambda v: wilson.apply_Ddag(U, v, dims, 0.124, hop_sign=+1)  # noqa: E731
+    xo, it, oinfo = cg.cgnr(D, Dd, b, tol=1e-10)
+    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+    assert rel(x, xo) <= max(1e-9, 2e-10 * cond)
+    assert abs(info[0]["iters"] - it) <= 1
+
+
 def test_deterministic_bitwise(env):
     dims = (4, 6, 8, 10)
     U = gauge(dims, 12)

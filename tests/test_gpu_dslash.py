@@ -132,6 +132,25 @@ def test_dslash_384_site_bricks(torch_dev, wd, monkeypatch, prec, nrhs):
             assert site_rel_err(got[k], op(U, psi[k], dims, 0.1245)) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_plus_kappa_lattice(torch_dev, wd, prec):
+    """WD_SIGN_PLUS_KAPPA: D = 1 + kappa (hops) as printed in Eq. (1)."""
+    torch, dev = torch_dev
+    dims = (4, 6, 8, 10)
+    U = gauge(dims, 35)
+    psi = synth.gaussian_spinor(dims, 36)
+    lat = wd.Lattice(dims, plus_kappa=True)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    pd = torch.from_numpy(psi).to(dev)
+    for dagger in (0, 1):
+        od = torch.full_like(pd, float("nan"))
+        lat.apply(0.1245, pd, od, prec=prec, dagger=dagger)
+        torch.cuda.synchronize()
+        op = wilson.apply_Ddag if dagger else wilson.apply_D
+        assert site_rel_err(od.cpu().numpy(), op(U, psi, dims, 0.1245, hop_sign=+1)) <= TOL[prec]
+    lat.close()
+
+
 def test_point_source_zero_sites_exact(torch_dev, wd):
     torch, dev = torch_dev
     dims = (4, 6, 8, 10)
