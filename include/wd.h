@@ -78,10 +78,14 @@ enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 };
  * eps(x) = (-1)^(x+y+z+t): same spectrum, solutions differ by eps. */
 enum { WD_BC_ANTIPERIODIC_T = 1u << 0, WD_SIGN_PLUS_KAPPA = 1u << 1 };
 
-/* Normal-equation forms of the CG solve (Sec. 2.2). */
+/* Normal-equation forms of the CG solve (Sec. 2.2), optionally on the
+ * even-odd Schur complement: with WD_SOLVE_EVEN_ODD or'ed in, CG runs on
+ * M = 1 - D_eo D_oe for the even sites (b^_e = b_e - D_eo b_o) and the odd
+ * sites follow as x_o = b_o - D_oe x_e. */
 enum {
-    WD_FORM_CGNR = 0, /* D^dag D x = D^dag b */
-    WD_FORM_CGNE = 1  /* the paper's listing: D D^dag y = b, x = D^dag y */
+    WD_FORM_CGNR = 0,          /* D^dag D x = D^dag b */
+    WD_FORM_CGNE = 1,          /* the paper's listing: D D^dag y = b, x = D^dag y */
+    WD_SOLVE_EVEN_ODD = 1 << 8 /* flag: the same forms with M in place of D */
 };
 
 /* ---------------------------------------------------------------- lattice */
@@ -125,6 +129,16 @@ int wd_apply_D(wd_lattice *lat, double kappa, int prec, const double *in, double
 int wd_apply_Ddag(wd_lattice *lat, double kappa, int prec, const double *in, double *out,
                   void *stream);
 
+/* Even-odd (Schur complement) operator: out = M in (dagger = 0) or M^dag in
+ * (dagger = 1) with M = 1 - D_eo D_oe on the even sites (parity
+ * (x+y+z+t) mod 2 = 0), D_eo / D_oe the blocks of D between even and odd
+ * sites.  Canonical float64 device spinors [nrhs][V][24]; odd sites of in
+ * are ignored and odd sites of out are set to zero.  Needs bricks with an
+ * even x extent (the default choice).  Stream-ordered; allocates its
+ * workspace stream-ordered. */
+int wd_apply_schur(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs,
+                   const double *in, double *out, void *stream);
+
 /* Batched form: nrhs (1..12) canonical spinors stacked as [rhs][V][24].  The
  * workgroups of all right-hand sides on the same sites run side by side, so
  * a gauge link is read from HBM about once per site for all of them. */
@@ -163,7 +177,8 @@ typedef struct {
     double reliable_delta;     /* mixed: update when ||r_lo|| < delta * max||r_lo|| (<= 0: 0.1) */
     int32_t x0_given;          /* 1: x holds a starting guess on entry; 0: start from x = 0
                                   (CGNR only: CGNE always starts from y = 0) */
-    int32_t form;              /* WD_FORM_CGNR (0) or WD_FORM_CGNE (1) */
+    int32_t form;              /* WD_FORM_CGNR (0) or WD_FORM_CGNE (1), optionally
+                                  | WD_SOLVE_EVEN_ODD */
 } wd_solve_params;
 
 typedef struct {
@@ -171,7 +186,8 @@ typedef struct {
     int32_t iters;            /* CG iterations (inner iterations for mixed) */
     int32_t reliable_updates; /* FP64 true-residual recomputations (incl. the final check) */
     double true_rel_resid;    /* FP64: ||D^dag b - D^dag D x|| / ||D^dag b|| (CGNR),
-                                 ||b - D D^dag y|| / ||b|| (CGNE) */
+                                 ||b - D D^dag y|| / ||b|| (CGNE); with
+                                 WD_SOLVE_EVEN_ODD the same with M, b^_e, x_e */
     double rel_resid_D;       /* ||b - D x|| / ||b|| in FP64 */
     double seconds;           /* wall time of the solve (submit to completion when served) */
     double queued_seconds;    /* served: submission to admission; 0 for wd_cg_solve */

@@ -40,6 +40,7 @@ WD_F64, WD_F32, WD_F16 = 0, 1, 2
 WD_BC_ANTIPERIODIC_T = 1
 WD_SIGN_PLUS_KAPPA = 2
 WD_FORM_CGNR, WD_FORM_CGNE = 0, 1
+WD_SOLVE_EVEN_ODD = 1 << 8
 FORM = {"cgnr": WD_FORM_CGNR, "cgne": WD_FORM_CGNE, WD_FORM_CGNR: WD_FORM_CGNR,
         WD_FORM_CGNE: WD_FORM_CGNE}
 
@@ -87,6 +88,7 @@ _SIGS = {
     "wd_apply_D": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp],
     "wd_apply_Ddag": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp],
     "wd_apply": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
+    "wd_apply_schur": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
     "wd_field_create": [_vp, _i32, _i32, ctypes.POINTER(_vp)],
     "wd_field_destroy": [_vp],
     "wd_field_import": [_vp, _vp, _vp],
@@ -202,6 +204,12 @@ def wd_apply(h, kappa, prec, dagger, nrhs, inp, out, volume, stream=None):
                         _dptr(inp, n, "in"), _dptr(out, n, "out"), _stream(stream)))
 
 
+def wd_apply_schur(h, kappa, prec, dagger, nrhs, inp, out, volume, stream=None):
+    n = volume * 24 * nrhs
+    _check(lib.wd_apply_schur(h, float(kappa), PREC[prec], int(dagger), int(nrhs),
+                              _dptr(inp, n, "in"), _dptr(out, n, "out"), _stream(stream)))
+
+
 def wd_apply_D(h, kappa, prec, inp, out, volume, stream=None):
     _check(lib.wd_apply_D(h, float(kappa), PREC[prec], _dptr(inp, volume * 24, "in"),
                           _dptr(out, volume * 24, "out"), _stream(stream)))
@@ -213,10 +221,12 @@ def wd_apply_Ddag(h, kappa, prec, inp, out, volume, stream=None):
 
 
 def make_params(kappa, tol=1e-10, max_iter=20000, prec="f64", nrhs=1, reliable_max_iter=50,
-                reliable_delta=0.1, x0_given=False, form="cgnr"):
+                reliable_delta=0.1, x0_given=False, form="cgnr", even_odd=False):
+    f = FORM[form] if form in FORM else int(form)
+    if even_odd:
+        f |= WD_SOLVE_EVEN_ODD
     return wd_solve_params(float(kappa), float(tol), int(max_iter), PREC[prec], int(nrhs),
-                           int(reliable_max_iter), float(reliable_delta), 1 if x0_given else 0,
-                           FORM[form] if form in FORM else int(form))
+                           int(reliable_max_iter), float(reliable_delta), 1 if x0_given else 0, f)
 
 
 def wd_cg_solve(h, params: wd_solve_params, b, x, volume, stream=None):
@@ -266,11 +276,14 @@ class Lattice:
     def apply(self, kappa, inp, out, prec="f64", dagger=False, nrhs=1, stream=None):
         wd_apply(self.handle, kappa, prec, dagger, nrhs, inp, out, self.volume, stream)
 
+    def apply_schur(self, kappa, inp, out, prec="f64", dagger=False, nrhs=1, stream=None):
+        wd_apply_schur(self.handle, kappa, prec, dagger, nrhs, inp, out, self.volume, stream)
+
     def solve(self, b, x, kappa, tol=1e-10, prec="f64", nrhs=1, max_iter=20000,
               reliable_max_iter=50, reliable_delta=0.1, x0_given=False, form="cgnr",
-              stream=None):
+              even_odd=False, stream=None):
         p = make_params(kappa, tol, max_iter, prec, nrhs, reliable_max_iter, reliable_delta,
-                        x0_given, form)
+                        x0_given, form, even_odd)
         return wd_cg_solve(self.handle, p, b, x, self.volume, stream)
 
     def close(self):
@@ -332,9 +345,10 @@ class Server:
         self._keep = {}
 
     def submit(self, lattice: Lattice, b, x, kappa, tol=1e-10, prec="f32", nrhs=1,
-               max_iter=20000, reliable_max_iter=50, reliable_delta=0.1, form="cgnr") -> int:
+               max_iter=20000, reliable_max_iter=50, reliable_delta=0.1, form="cgnr",
+               even_odd=False) -> int:
         p = make_params(kappa, tol, max_iter, prec, nrhs, reliable_max_iter, reliable_delta,
-                        form=form)
+                        form=form, even_odd=even_odd)
         n = lattice.volume * 24 * nrhs
         # the server reads b on its own stream: make the caller's writes visible
         _torch().cuda.current_stream().synchronize()

@@ -103,6 +103,31 @@ void launch_gauge_lo(const void *g64, void *glo, int prec, int V, hipStream_t s)
         hipLaunchKernelGGL(k_gauge_lo<WD_F16>, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s, g64, glo, V);
 }
 
+// even-odd: links of the parity-p sites in the half layout and format PREC
+template <int PREC>
+__global__ void k_gauge_split(const void *__restrict__ g, void *__restrict__ o, int p, Geom geo) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= geo.V / 2) return;
+    const int i = site_of_half(geo, h, p);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        cx<double> u[9];
+        Link<WD_F64>::load(g, mu, i, u);
+        Link<PREC>::store(o, mu, h, u);
+    }
+}
+
+void launch_gauge_split(const void *g64, void *half, int prec, int p, const Geom &geo,
+                        hipStream_t s) {
+    const dim3 gr(blocks_for(geo.V / 2, kBS)), bs(kBS);
+    if (prec == WD_F64)
+        hipLaunchKernelGGL(k_gauge_split<WD_F64>, gr, bs, 0, s, g64, half, p, geo);
+    else if (prec == WD_F32)
+        hipLaunchKernelGGL(k_gauge_split<WD_F32>, gr, bs, 0, s, g64, half, p, geo);
+    else
+        hipLaunchKernelGGL(k_gauge_split<WD_F16>, gr, bs, 0, s, g64, half, p, geo);
+}
+
 // ------------------------------------------------------------------ spinors
 
 template <int PREC>
@@ -154,6 +179,39 @@ __global__ void k_export(FieldRef f, double2 *__restrict__ canon, Geom geo) {
     coords_of(geo, i, x, y, z, t);
     cx<double> v[12];
     load_as_double<PREC>(rhs_view(f, r), i, v);
+    double2 *dst = canon + ((size_t)r * geo.V + lex_of(geo, x, y, z, t)) * 12;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) dst[k] = make_double2(v[k].re, v[k].im);
+}
+
+// canonical [rhs][s][12] <-> half field of parity p (entry h: site
+// site_of_half(h, p)); f.V = V / 2
+template <int PREC>
+__global__ void k_import_half(const double2 *__restrict__ canon, FieldRef f, int p, Geom geo) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= f.V) return;
+    const int r = blockIdx.y;
+    int x, y, z, t;
+    coords_of(geo, site_of_half(geo, h, p), x, y, z, t);
+    const double2 *src = canon + ((size_t)r * geo.V + lex_of(geo, x, y, z, t)) * 12;
+    cx<double> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        double2 d = src[k];
+        v[k] = {d.x, d.y};
+    }
+    store_from_double<PREC>(rhs_view(f, r), h, v);
+}
+
+template <int PREC>
+__global__ void k_export_half(FieldRef f, double2 *__restrict__ canon, int p, Geom geo) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= f.V) return;
+    const int r = blockIdx.y;
+    int x, y, z, t;
+    coords_of(geo, site_of_half(geo, h, p), x, y, z, t);
+    cx<double> v[12];
+    load_as_double<PREC>(rhs_view(f, r), h, v);
     double2 *dst = canon + ((size_t)r * geo.V + lex_of(geo, x, y, z, t)) * 12;
 #pragma unroll
     for (int k = 0; k < 12; ++k) dst[k] = make_double2(v[k].re, v[k].im);
@@ -221,6 +279,16 @@ void launch_import(const double *canon, FieldRef f, const Geom &geo, hipStream_t
 void launch_export(FieldRef f, double *canon, const Geom &geo, hipStream_t s) {
     WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_export<PP>, field_grid(f), dim3(kSiteBlock), 0,
                                                 s, f, (double2 *)canon, geo));
+}
+
+void launch_import_half(const double *canon, FieldRef f, int p, const Geom &geo, hipStream_t s) {
+    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_import_half<PP>, field_grid(f), dim3(kSiteBlock),
+                                                0, s, (const double2 *)canon, f, p, geo));
+}
+
+void launch_export_half(FieldRef f, double *canon, int p, const Geom &geo, hipStream_t s) {
+    WD_DISPATCH_PREC(f.prec, hipLaunchKernelGGL(k_export_half<PP>, field_grid(f), dim3(kSiteBlock),
+                                                0, s, f, (double2 *)canon, p, geo));
 }
 
 template <int SRC>

@@ -366,6 +366,8 @@ __device__ inline void finalize_rhs(const RedArgs &red, int r, double total) {
             break;
         case RED_AUX: st.aux = total; break;
         case RED_AUX2: st.aux2 = total; break;
+        case RED_AUX_ADD: st.aux += total; break;
+        case RED_AUX2_ADD: st.aux2 += total; break;
         default: break;
     }
 }

@@ -562,4 +562,118 @@ void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, F
     }
 }
 
+// Even-odd hopping term on half fields (one lane per site of one rhs):
+//   out_p = cs * c_p - k * H_{p,1-p} in_{1-p}
+// with H the hop sum of Eq. (1) (projectors exchanged for DAG).  Entry h of a
+// half field is site site_of_half(h, p); the neighbours, of the other
+// parity, sit at their internal index >> 1.  Forward links come from the
+// parity-p half array gp, backward links U_mu(x - mu) from gq.  The hops are
+// summed in the order of the full stencil.
+template <int PREC, bool DAG, bool RED, bool HASC, int GROUP>
+__global__ void __launch_bounds__(256) k_hop_half(Geom g, const void *__restrict__ gp,
+                                                  const void *__restrict__ gq, int p, FieldRef in,
+                                                  FieldRef c, FieldRef out, double k_d,
+                                                  double cs_d, RedArgs red, Gate gate) {
+    using R = typename Spinor<PREC>::R;
+    if (gate_off(gate)) return;  // grid-uniform
+    const int nrhs = in.nrhs;
+    const int lb = logical_block();
+    const int sb = lb / nrhs;
+    const int rhs = lb - sb * nrhs;
+    if (!gate_rhs(gate, rhs)) return;  // workgroup-uniform
+    const FieldRef fin = rhs_view(in, rhs);
+    const int h = sb * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (h < out.V) {
+        const int i = site_of_half(g, h, p);
+        const Nbrs nb = neighbours(g, i);
+        const bool neg_tp = g.antiperiodic && nb.cross_tp;
+        const bool neg_tm = g.antiperiodic && nb.cross_tm;
+        cx<R> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+        constexpr int SF = DAG ? +1 : -1;
+        constexpr int SB = -SF;
+#define WD_HOP_FENCE(k) \
+    if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
+        hop<0, SF, false, PREC>(gp, fin, nb.xp >> 1, h, false, acc);
+        WD_HOP_FENCE(1);
+        hop<0, SB, true, PREC>(gq, fin, nb.xm >> 1, nb.xm >> 1, false, acc);
+        WD_HOP_FENCE(2);
+        hop<1, SF, false, PREC>(gp, fin, nb.yp >> 1, h, false, acc);
+        WD_HOP_FENCE(3);
+        hop<1, SB, true, PREC>(gq, fin, nb.ym >> 1, nb.ym >> 1, false, acc);
+        WD_HOP_FENCE(4);
+        hop<2, SF, false, PREC>(gp, fin, nb.zp >> 1, h, false, acc);
+        WD_HOP_FENCE(5);
+        hop<2, SB, true, PREC>(gq, fin, nb.zm >> 1, nb.zm >> 1, false, acc);
+        WD_HOP_FENCE(6);
+        hop<3, SF, false, PREC>(gp, fin, nb.tp >> 1, h, neg_tp, acc);
+        WD_HOP_FENCE(7);
+        hop<3, SB, true, PREC>(gq, fin, nb.tm >> 1, nb.tm >> 1, neg_tm, acc);
+        WD_HOP_FENCE(8);
+#undef WD_HOP_FENCE
+        cx<R> o[12];
+        if constexpr (HASC) {
+            Spinor<PREC>::load(rhs_view(c, rhs), h, o);
+            const R cs = (R)cs_d;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) o[k] = scale(cs, o[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) o[k] = {R(0), R(0)};
+        }
+        const R kk = (R)k_d;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            o[k] = o[k] - scale(kk, acc[k]);
+            if (RED) nrm += (double)o[k].re * (double)o[k].re + (double)o[k].im * (double)o[k].im;
+        }
+        Spinor<PREC>::store(rhs_view(out, rhs), h, o);
+    }
+    if (RED) reduce_block(nrm, red.partials, (size_t)sb * nrhs + rhs);
+}
+
+template <int PREC, bool DAG, bool RED, bool HASC>
+static void launch_hop_half_k(dim3 grid, hipStream_t s, const Geom &g, const void *gp,
+                              const void *gq, int p, FieldRef in, FieldRef c, FieldRef out,
+                              double k, double cs, const RedArgs &r, Gate gate) {
+    constexpr int G = HopGroup<PREC>::value;
+    hipLaunchKernelGGL((k_hop_half<PREC, DAG, RED, HASC, G>), grid, dim3(kSiteBlock), 0, s, g, gp,
+                       gq, p, in, c, out, k, cs, r, gate);
+}
+
+template <int PREC>
+static void launch_hop_half_prec(const Geom &g, const void *gp, const void *gq, int p, double k,
+                                 double cs, int dagger, FieldRef in, FieldRef c, FieldRef out,
+                                 const RedArgs *red, Gate gate, hipStream_t s) {
+    const int nb = site_blocks(out.V);
+    const dim3 grid(nb * in.nrhs);
+    RedArgs r{};
+    if (red) r = *red;
+    const bool hc = c.data != nullptr;
+    const int sel = (dagger ? 4 : 0) | (red ? 2 : 0) | (hc ? 1 : 0);
+    switch (sel) {
+        case 0: launch_hop_half_k<PREC, false, false, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 1: launch_hop_half_k<PREC, false, false, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 2: launch_hop_half_k<PREC, false, true, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 3: launch_hop_half_k<PREC, false, true, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 4: launch_hop_half_k<PREC, true, false, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 5: launch_hop_half_k<PREC, true, false, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 6: launch_hop_half_k<PREC, true, true, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        default: launch_hop_half_k<PREC, true, true, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+    }
+    if (red) launch_finalize(r, nb, gate.batch ? gate.mode : -1, s);
+}
+
+void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, double k, double cs,
+                     int dagger, FieldRef in, FieldRef c, FieldRef out, const RedArgs *red,
+                     Gate gate, hipStream_t s) {
+    switch (in.prec) {
+        case WD_F64: launch_hop_half_prec<WD_F64>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
+        case WD_F32: launch_hop_half_prec<WD_F32>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
+        default: launch_hop_half_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
+    }
+}
+
 }  // namespace wd

@@ -76,6 +76,42 @@ void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err) {
     return p;
 }
 
+bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[2]) {
+    std::lock_guard<std::mutex> lk(lat->mu);
+    if (!lat->has_gauge) {
+        *err = fail(WD_ERR_NOGAUGE, "gauge field not set (call wd_set_gauge first)");
+        return false;
+    }
+    if (!eo_supported(lat->g)) {
+        *err = fail(WD_ERR_ARG, "even-odd needs bricks with an even x extent (got %d)", lat->g.tx);
+        return false;
+    }
+    if (!lat->gauge_eo[prec][0]) {
+        void *h[2] = {nullptr, nullptr};
+        const size_t bytes = gauge_bytes(prec, lat->g.V / 2);
+        for (int p = 0; p < 2; ++p) {
+            if (hipMalloc(&h[p], bytes) != hipSuccess) {
+                if (h[0]) (void)hipFree(h[0]);
+                *err = fail(WD_ERR_NOMEM, "hipMalloc of an even-odd gauge form failed");
+                return false;
+            }
+        }
+        for (int p = 0; p < 2; ++p) launch_gauge_split(lat->gauge[WD_F64], h[p], prec, p, lat->g, s);
+        // other streams (server slots) may use the form next: finish building it
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipFree(h[0]);
+            (void)hipFree(h[1]);
+            *err = fail(WD_ERR_HIP, "building an even-odd gauge form failed");
+            return false;
+        }
+        lat->gauge_eo[prec][0] = h[0];
+        lat->gauge_eo[prec][1] = h[1];
+    }
+    out[0] = lat->gauge_eo[prec][0];
+    out[1] = lat->gauge_eo[prec][1];
+    return true;
+}
+
 // ------------------------------------------------------------------ timing
 
 struct TimingRec {
@@ -141,6 +177,30 @@ void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const 
     g_pending.push_back({names[in.prec], a, b});
 }
 
+void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
+              const FieldRef &in, const FieldRef &c, const FieldRef &out, const RedArgs *red,
+              Gate gate, hipStream_t s) {
+    // D_{p,1-p} = hop_sign * kappa * H_{p,1-p}; the kernel computes cs c - k H in
+    const double k = -lat->hop_sign * kappa;
+    if (!g_timing.load(std::memory_order_relaxed)) {
+        launch_hop_half(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, out, red, gate, s);
+        return;
+    }
+    static const char *names[3] = {"eo_f64", "eo_f32", "eo_f16"};
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        if (g_pending.size() > 4096) drain_pending_locked();
+        a = take_event();
+        b = take_event();
+    }
+    (void)hipEventRecord(a, s);
+    launch_hop_half(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, out, red, gate, s);
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back({names[in.prec], a, b});
+}
+
 }  // namespace wd
 
 using namespace wd;
@@ -180,8 +240,11 @@ int wd_destroy_lattice(wd_lattice *lat) {
     if (!lat) return fail(WD_ERR_ARG, "null lattice");
     if (lat->users.load() != 0)
         return fail(WD_ERR_STATE, "lattice still has %d requests on a server", lat->users.load());
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 3; ++p) {
         if (lat->gauge[p]) (void)hipFree(lat->gauge[p]);
+        for (int q = 0; q < 2; ++q)
+            if (lat->gauge_eo[p][q]) (void)hipFree(lat->gauge_eo[p][q]);
+    }
     delete lat;
     return WD_OK;
 }
@@ -195,8 +258,10 @@ int wd_lattice_volume(const wd_lattice *lat, int64_t *volume) {
 int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes) {
     if (!lat || !bytes) return fail(WD_ERR_ARG, "null argument");
     size_t b = 0;
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 3; ++p) {
         if (lat->gauge[p]) b += gauge_bytes(p, lat->g.V);
+        if (lat->gauge_eo[p][0]) b += 2 * gauge_bytes(p, lat->g.V / 2);
+    }
     *bytes = b;
     return WD_OK;
 }
@@ -218,6 +283,10 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
     launch_pack_gauge_f64(U, lat->gauge[WD_F64], lat->g, s);
     for (int p = 1; p < 3; ++p)
         if (lat->gauge[p]) launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], p, lat->g.V, s);
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 2; ++q)
+            if (lat->gauge_eo[p][q])
+                launch_gauge_split(lat->gauge[WD_F64], lat->gauge_eo[p][q], p, q, lat->g, s);
     WD_LAUNCH_CHECK();
     WD_HIP_CHECK(hipStreamSynchronize(s));
     lat->has_gauge = true;
@@ -323,6 +392,46 @@ int wd_apply_D(wd_lattice *lat, double kappa, int prec, const double *in, double
 int wd_apply_Ddag(wd_lattice *lat, double kappa, int prec, const double *in, double *out,
                   void *stream) {
     return wd_apply(lat, kappa, prec, 1, 1, in, out, stream);
+}
+
+int wd_apply_schur(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs,
+                   const double *in, double *out, void *stream) {
+    if (!lat || !in || !out) return fail(WD_ERR_ARG, "null argument");
+    if (!valid_prec(prec)) return fail(WD_ERR_ARG, "unknown precision %d", prec);
+    if (nrhs < 1 || nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", nrhs);
+    if (!std::isfinite(kappa)) return fail(WD_ERR_ARG, "kappa not finite");
+    if (dagger != 0 && dagger != 1) return fail(WD_ERR_ARG, "dagger must be 0 or 1");
+    if (in == out) return fail(WD_ERR_ARG, "in and out must not overlap");
+    if (!eo_supported(lat->g))
+        return fail(WD_ERR_ARG, "even-odd needs bricks with an even x extent");
+    hipStream_t s = (hipStream_t)stream;
+    int err = WD_OK;
+    void *gh[2];
+    if (!gauge_eo_for(lat, prec, s, &err, gh)) return err;
+    const int Vh = lat->g.V / 2;
+    const size_t one = field_data_bytes(prec, Vh, nrhs) + 256;
+    void *mem = nullptr;
+    hipError_t he = hipMallocAsync(&mem, 3 * one, s);
+    if (he != hipSuccess)
+        return fail(WD_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s", 3 * one,
+                    hipGetErrorString(he));
+    char *cur = (char *)mem;
+    FieldRef ve = carve(cur, prec, nrhs, Vh);
+    cur = (char *)mem + one;
+    FieldRef to = carve(cur, prec, nrhs, Vh);
+    cur = (char *)mem + 2 * one;
+    FieldRef oe = carve(cur, prec, nrhs, Vh);
+    const Gate none{nullptr, nullptr, GATE_ACTIVE};
+    launch_import_half(in, ve, 0, lat->g, s);
+    // t_o = D_oe v_e ; out_e = v_e - D_eo t_o  (D^dag's blocks for dagger)
+    hop_half(lat, gh, 1, kappa, 0.0, dagger, ve, FieldRef{}, to, nullptr, none, s);
+    hop_half(lat, gh, 0, -kappa, 1.0, dagger, to, ve, oe, nullptr, none, s);
+    launch_export_half(oe, out, 0, lat->g, s);
+    launch_zero(to, s);
+    launch_export_half(to, out, 1, lat->g, s);  // odd sites of out = 0
+    (void)hipFreeAsync(mem, s);
+    WD_LAUNCH_CHECK();
+    return WD_OK;
 }
 
 int wd_timing_enable(int on) {

@@ -15,6 +15,7 @@
 struct wd_lattice {
     wd::Geom g{};
     void *gauge[3] = {nullptr, nullptr, nullptr};  // F64-18, F32-12, F16-12
+    void *gauge_eo[3][2] = {};                     // even-odd halves [prec][parity]
     bool has_gauge = false;
     double hop_sign = -1.0;  // D = 1 + hop_sign * kappa * (hops); kernels take 1 - kappa' H
     std::mutex mu;
@@ -56,6 +57,17 @@ bool valid_prec(int p);
 // packed gauge form for a precision, building the 12-real forms on first use
 // (enqueued on stream s).  Returns nullptr and sets the error on failure.
 void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err);
+
+// even-odd half forms of a precision (both parities), built on first use
+// from the F64-18 tiles; false and the error set on failure
+bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[2]);
+
+// out_p = cs * c_p + D_{p,1-p} in_{1-p} on half fields: the off-diagonal block
+// of D (D^dag for dagger) from parity 1-p to p at hopping parameter kappa
+// (the lattice's sign applied), plus an optional scaled c term
+void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
+              const FieldRef &in, const FieldRef &c, const FieldRef &out, const RedArgs *red,
+              Gate gate, hipStream_t s);
 
 // stencil launch with optional event timing
 void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
@@ -107,6 +119,8 @@ class Solve {
     };
     void enqueue_inner(int iters);
     void enqueue_reliable();
+    void op(bool first, const FieldRef &in, const FieldRef &out, const RedArgs *red, Gate gate,
+            bool lo);
     void enqueue_finish();
     int push_status();
     RedArgs red(int mode) const;
@@ -118,14 +132,17 @@ class Solve {
     double *x_;
     hipStream_t s_ = nullptr;
     int prec_;
-    int d1_ = 0, d2_ = 1;  // daggers of the two stencils of the normal operator
+    int d1_ = 0, d2_ = 1;  // daggers of the two operators of the normal equations
+    bool eo_ = false;      // on the even-odd Schur complement
     int chunk_ = 8;
     int rel_every_ = 1;  // inner iterations between gated reliable updates
     void *gauge64_ = nullptr, *gauge_lo_ = nullptr;
+    void *gh64_[2] = {}, *ghlo_[2] = {};  // even-odd halves
     void *mem_ = nullptr;
     size_t bytes_ = 0;
     FieldRef b64_{}, bp_{}, x64_{}, r64_{}, t64_{}, ax64_{};
     FieldRef xl_{}, rl_{}, pl_{}, tl_{}, apl_{};
+    FieldRef bo64_{}, tmp64_{}, tmpl_{};  // even-odd: b_o and odd temporaries
     RhsState *st_ = nullptr;
     BatchState *batch_ = nullptr;
     double *partials_ = nullptr;

@@ -59,7 +59,8 @@ struct wd_server {
     struct LatUse {
         int users = 0;
         size_t charged = 0;
-        bool form[3] = {false, false, false};
+        bool form[3] = {false, false, false};  // full-lattice forms charged
+        bool eo[3] = {false, false, false};    // even-odd half forms charged
     };
     std::map<wd_lattice *, LatUse> lat_use;
     size_t used = 0, peak = 0;
@@ -73,21 +74,33 @@ static size_t request_bytes(const wd_lattice *lat, const wd_solve_params &p) {
     return Solve::footprint(lat, p);
 }
 
-static size_t lattice_gauge_charge(const wd_lattice *lat, int prec) {
-    size_t b = gauge_bytes(WD_F64, lat->g.V);
-    if (prec != WD_F64) b += gauge_bytes(prec, lat->g.V);
+static bool eo_request(const wd_solve_params &p) { return (p.form & WD_SOLVE_EVEN_ODD) != 0; }
+
+// gauge bytes a request needs on its lattice: the float64 tiles (always
+// there once the gauge is set), plus the forms its solve reads
+static size_t gauge_need(const wd_lattice *lat, const wd_solve_params &p, const bool form[3],
+                         const bool eo[3]) {
+    const int V = lat->g.V, prec = p.prec_inner;
+    size_t b = form[WD_F64] ? 0 : gauge_bytes(WD_F64, V);
+    if (eo_request(p)) {
+        if (!eo[WD_F64]) b += 2 * gauge_bytes(WD_F64, V / 2);
+        if (prec != WD_F64 && !eo[prec]) b += 2 * gauge_bytes(prec, V / 2);
+    } else if (prec != WD_F64 && !form[prec]) {
+        b += gauge_bytes(prec, V);
+    }
     return b;
 }
 
-// extra gauge bytes admitting a request of precision prec on lat would add
-static size_t gauge_extra(wd_server *s, wd_lattice *lat, int prec) {
+static size_t lattice_gauge_charge(const wd_lattice *lat, const wd_solve_params &p) {
+    const bool none[3] = {false, false, false};
+    return gauge_need(lat, p, none, none);
+}
+
+// extra gauge bytes admitting request p on lat would add
+static size_t gauge_extra(wd_server *s, wd_lattice *lat, const wd_solve_params &p) {
     auto it = s->lat_use.find(lat);
-    size_t b = 0;
-    const bool have64 = it != s->lat_use.end() && it->second.form[WD_F64];
-    const bool havep = it != s->lat_use.end() && it->second.form[prec];
-    if (!have64) b += gauge_bytes(WD_F64, lat->g.V);
-    if (prec != WD_F64 && !havep) b += gauge_bytes(prec, lat->g.V);
-    return b;
+    if (it == s->lat_use.end()) return lattice_gauge_charge(lat, p);
+    return gauge_need(lat, p, it->second.form, it->second.eo);
 }
 
 // have_info: the solve ran to completion and its device status is valid
@@ -123,7 +136,7 @@ static void scheduler(wd_server *s) {
         // admit in arrival order while budget and slots allow
         while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
             auto r = s->reqs[s->queue.front()];
-            const size_t extra = gauge_extra(s, r->lat, r->p.prec_inner);
+            const size_t extra = gauge_extra(s, r->lat, r->p);
             const size_t need = request_bytes(r->lat, r->p) + extra;
             if (s->used + need > s->cfg.hbm_budget_bytes) break;  // head of line waits
             s->queue.pop_front();
@@ -136,7 +149,12 @@ static void scheduler(wd_server *s) {
             lu.users += 1;
             lu.charged += extra;
             lu.form[WD_F64] = true;
-            lu.form[r->p.prec_inner] = true;
+            if (eo_request(r->p)) {
+                lu.eo[WD_F64] = true;
+                lu.eo[r->p.prec_inner] = true;
+            } else {
+                lu.form[r->p.prec_inner] = true;
+            }
             s->used += r->charged + extra;
             s->peak = std::max(s->peak, s->used);
             r->t_admit = now_seconds();
@@ -230,7 +248,7 @@ int wd_submit(wd_server *s, wd_lattice *lat, const wd_solve_params *p, const dou
     if (rc) return rc;
     if (!b || !x) return fail(WD_ERR_ARG, "null argument");
     if (b == x) return fail(WD_ERR_ARG, "b and x must not overlap");
-    const size_t need = request_bytes(lat, *p) + lattice_gauge_charge(lat, p->prec_inner);
+    const size_t need = request_bytes(lat, *p) + lattice_gauge_charge(lat, *p);
     if (need > s->cfg.hbm_budget_bytes)
         return fail(WD_ERR_NOMEM, "request needs %zu bytes, more than the whole budget (%zu)",
                     need, s->cfg.hbm_budget_bytes);

@@ -36,8 +36,10 @@ namespace wd {
 
 Solve::Solve(wd_lattice *lat, const wd_solve_params &p, const double *b, double *x)
     : lat_(lat), p_(p), b_(b), x_(x), prec_(p.prec_inner) {
-    // the normal operator as two stencils: D^dag D (CGNR) or D D^dag (CGNE)
-    d1_ = p.form == WD_FORM_CGNE ? 1 : 0;
+    // the normal operator as two applications: A^dag A (CGNR) or A A^dag
+    // (CGNE), A = D, or the Schur complement M with WD_SOLVE_EVEN_ODD
+    eo_ = (p.form & WD_SOLVE_EVEN_ODD) != 0;
+    d1_ = (p.form & 0xff) == WD_FORM_CGNE ? 1 : 0;
     d2_ = 1 - d1_;
 }
 
@@ -76,10 +78,13 @@ int Solve::validate(wd_lattice *lat, const wd_solve_params *p) {
     if (!valid_prec(p->prec_inner)) return fail(WD_ERR_ARG, "unknown precision %d", p->prec_inner);
     if (p->nrhs < 1 || p->nrhs > 12) return fail(WD_ERR_ARG, "nrhs = %d outside 1..12", p->nrhs);
     if (p->x0_given != 0 && p->x0_given != 1) return fail(WD_ERR_ARG, "x0_given must be 0 or 1");
-    if (p->form != WD_FORM_CGNR && p->form != WD_FORM_CGNE)
+    const int base = p->form & ~WD_SOLVE_EVEN_ODD;
+    if (base != WD_FORM_CGNR && base != WD_FORM_CGNE)
         return fail(WD_ERR_ARG, "unknown form %d", p->form);
-    if (p->form == WD_FORM_CGNE && p->x0_given)
+    if (base == WD_FORM_CGNE && p->x0_given)
         return fail(WD_ERR_ARG, "a starting guess needs the CGNR form");
+    if ((p->form & WD_SOLVE_EVEN_ODD) && !eo_supported(lat->g))
+        return fail(WD_ERR_ARG, "even-odd needs bricks with an even x extent");
     if (!lat->has_gauge) return fail(WD_ERR_NOGAUGE, "gauge field not set");
     return WD_OK;
 }
@@ -91,11 +96,14 @@ static size_t field_bytes(int prec, int V, int nrhs) {
 }
 
 size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
-    const int V = lat->g.V, nr = p.nrhs;
+    const bool eo = (p.form & WD_SOLVE_EVEN_ODD) != 0;
+    const int V = eo ? lat->g.V / 2 : lat->g.V, nr = p.nrhs;
     const int lo = p.prec_inner;
     const int lo_xr = lo == WD_F16 ? WD_F32 : lo;
-    size_t b = 6 * field_bytes(WD_F64, V, nr);
-    b += 2 * field_bytes(lo_xr, V, nr) + 3 * field_bytes(lo, V, nr);
+    // float64: b, b', x, r, t, Ax (+ b_o and an odd temporary for even-odd)
+    size_t b = (eo ? 8 : 6) * field_bytes(WD_F64, V, nr);
+    // inner: x, r in lo_xr; p, t, Ap (+ an odd temporary) in lo
+    b += 2 * field_bytes(lo_xr, V, nr) + (eo ? 4 : 3) * field_bytes(lo, V, nr);
     b += align256((size_t)reduce_partials_cap(lat->g, p.nrhs) * sizeof(double));
     b += align256(sizeof(RhsState) * 12) + 256;
     return b;
@@ -103,17 +111,22 @@ size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
 
 int Solve::setup(hipStream_t stream, SlotRes *res) {
     s_ = stream;
-    const int V = lat_->g.V;
+    const int V = eo_ ? lat_->g.V / 2 : lat_->g.V;  // sites of the solved fields
     const int nrhs = p_.nrhs;
     const int64_t n = (int64_t)V * nrhs;
     int err = WD_OK;
-    gauge64_ = gauge_for(lat_, WD_F64, s_, &err);
-    if (!gauge64_) return err;
-    if (prec_ != WD_F64) {
-        gauge_lo_ = gauge_for(lat_, prec_, s_, &err);
-        if (!gauge_lo_) return err;
+    if (eo_) {
+        if (!gauge_eo_for(lat_, WD_F64, s_, &err, gh64_)) return err;
+        if (!gauge_eo_for(lat_, prec_, s_, &err, ghlo_)) return err;
     } else {
-        gauge_lo_ = gauge64_;
+        gauge64_ = gauge_for(lat_, WD_F64, s_, &err);
+        if (!gauge64_) return err;
+        if (prec_ != WD_F64) {
+            gauge_lo_ = gauge_for(lat_, prec_, s_, &err);
+            if (!gauge_lo_) return err;
+        } else {
+            gauge_lo_ = gauge64_;
+        }
     }
     bytes_ = footprint(lat_, p_);
     hipError_t he = hipMallocAsync(&mem_, bytes_, s_);
@@ -136,12 +149,17 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     r64_ = next(WD_F64);
     t64_ = next(WD_F64);
     ax64_ = next(WD_F64);
+    if (eo_) {
+        bo64_ = next(WD_F64);
+        tmp64_ = next(WD_F64);
+    }
     const int lo_xr = prec_ == WD_F16 ? WD_F32 : prec_;
     xl_ = next(lo_xr);
     rl_ = next(lo_xr);
     pl_ = next(prec_);
     tl_ = next(prec_);
     apl_ = next(prec_);
+    if (eo_) tmpl_ = next(prec_);
     partials_ = (double *)cur;
     partials_cap_ = (int)reduce_partials_cap(lat_->g, nrhs);
     cur += align256((size_t)partials_cap_ * sizeof(double));
@@ -188,20 +206,51 @@ RedArgs Solve::red(int mode) const {
     return r;
 }
 
+// One application of the operator A of the normal equations (first: the
+// one applied to p, giving t; else the one applied to t): D or D^dag, or on
+// the even sites M = 1 - D_eo D_oe or M^dag (two half-field stencils through
+// an odd temporary); red fuses |out|^2 into the last launch.
+void Solve::op(bool first, const FieldRef &in, const FieldRef &out, const RedArgs *red, Gate gate,
+               bool lo) {
+    const double k = p_.kappa;
+    const int dag = first ? d1_ : d2_;
+    if (!eo_) {
+        dslash(lat_, lo ? gauge_lo_ : gauge64_, k, dag, in, out, red, gate, s_);
+        return;
+    }
+    void *const *gh = lo ? ghlo_ : gh64_;
+    const FieldRef &tmp = lo ? tmpl_ : tmp64_;
+    hop_half(lat_, gh, 1, k, 0.0, dag, in, FieldRef{}, tmp, nullptr, gate, s_);  // D_oe in
+    hop_half(lat_, gh, 0, -k, 1.0, dag, tmp, in, out, red, gate, s_);           // in - D_eo tmp
+}
+
 int Solve::start() {
     const double k = p_.kappa;
     const Gate none{nullptr, nullptr, GATE_ACTIVE};
     launch_init_state(st_, batch_, p_.nrhs, s_);
-    launch_import(b_, b64_, lat_->g, s_);
     RedArgs rb = red(RED_B0);
-    if (p_.form == WD_FORM_CGNE)
-        launch_residual(bp_, b64_, FieldRef{}, rb, none, s_);  // b' = b, |b|^2
+    // b' = A^dag b^ (CGNR) or b^ (CGNE), |b'|^2; b^ = b, or b_e - D_eo b_o
+    FieldRef bh = b64_;
+    if (eo_) {
+        launch_import_half(b_, b64_, 0, lat_->g, s_);
+        launch_import_half(b_, bo64_, 1, lat_->g, s_);
+        hop_half(lat_, gh64_, 0, -k, 1.0, 0, bo64_, b64_, t64_, nullptr, none, s_);
+        bh = t64_;
+    } else {
+        launch_import(b_, b64_, lat_->g, s_);
+    }
+    if (d1_ == 1)
+        launch_residual(bp_, bh, FieldRef{}, rb, none, s_);  // CGNE: b' = b^
     else
-        dslash(lat_, gauge64_, k, 1, b64_, bp_, &rb, none, s_);  // b' = D^dag b, |b'|^2
-    if (p_.x0_given)
-        launch_import(x_, x64_, lat_->g, s_);
-    else
+        op(false, bh, bp_, &rb, none, false);                 // CGNR: b' = A^dag b^
+    if (p_.x0_given) {
+        if (eo_)
+            launch_import_half(x_, x64_, 0, lat_->g, s_);
+        else
+            launch_import(x_, x64_, lat_->g, s_);
+    } else {
         launch_zero(x64_, s_);
+    }
     launch_zero(xl_, s_);
     // the first reliable update forms r and p for every rhs with b' != 0
     if (p_.x0_given) {
@@ -219,13 +268,12 @@ int Solve::start() {
 }
 
 void Solve::enqueue_inner(int iters) {
-    const double k = p_.kappa;
     const Gate g = gate();
     RedArgs ra = red(RED_ALPHA);
     RedArgs rr = red(RED_RR);
     for (int i = 0; i < iters; ++i) {
-        dslash(lat_, gauge_lo_, k, d1_, pl_, tl_, &ra, g, s_);
-        dslash(lat_, gauge_lo_, k, d2_, tl_, apl_, nullptr, g, s_);
+        op(true, pl_, tl_, &ra, g, true);
+        op(false, tl_, apl_, nullptr, g, true);
         launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
         launch_update_p(pl_, rl_, g, s_);
         if ((i + 1) % rel_every_ == 0 || i + 1 == iters) enqueue_reliable();
@@ -236,13 +284,12 @@ void Solve::enqueue_inner(int iters) {
 // unfinished rhs is frozen and at least one waits for it; then it takes the
 // waiting rhs, and resets r_lo and p of those it restarts (GATE_RESTART).
 void Solve::enqueue_reliable() {
-    const double k = p_.kappa;
     const Gate trig{st_, batch_, GATE_TRIGGER};
     const Gate rst{st_, batch_, GATE_RESTART};
     RedArgs rt = red(RED_TRUE);
     launch_accum_zero(x64_, xl_, trig, s_);
-    dslash(lat_, gauge64_, k, d1_, x64_, t64_, nullptr, trig, s_);
-    dslash(lat_, gauge64_, k, d2_, t64_, ax64_, nullptr, trig, s_);
+    op(true, x64_, t64_, nullptr, trig, false);
+    op(false, t64_, ax64_, nullptr, trig, false);
     launch_residual(r64_, bp_, ax64_, rt, trig, s_);
     launch_convert(r64_, rl_, rst, s_);
     launch_restart_p(pl_, rl_, rst, s_);
@@ -253,18 +300,33 @@ void Solve::enqueue_finish() {
     const Gate none{nullptr, nullptr, GATE_ACTIVE};
     launch_accum_zero(x64_, xl_, Gate{st_, nullptr, GATE_ACTIVE}, s_);  // unconverged rhs
     RedArgs ra = red(RED_AUX);
+    RedArgs ra2 = red(RED_AUX_ADD);
     RedArgs rb = red(RED_AUX2);
-    if (p_.form == WD_FORM_CGNE) {
-        dslash(lat_, gauge64_, k, 1, x64_, t64_, nullptr, none, s_);  // x = D^dag y
-        dslash(lat_, gauge64_, k, 0, t64_, r64_, nullptr, none, s_);
-        launch_residual(ax64_, b64_, r64_, ra, none, s_);  // |b - D x|^2
-        launch_norm(b64_, rb, s_);                          // |b|^2
-        launch_export(t64_, x_, lat_->g, s_);
+    RedArgs rb2 = red(RED_AUX2_ADD);
+    // the solution of A z = b^: z = x (CGNR) or A^dag y (CGNE)
+    FieldRef z = x64_;
+    if (d1_ == 1) {
+        op(true, x64_, t64_, nullptr, none, false);
+        z = t64_;
+    }
+    if (eo_) {
+        // x_o = b_o - D_oe x_e, then |b - D x|^2 over both halves
+        const FieldRef xo = r64_;
+        hop_half(lat_, gh64_, 1, -k, 1.0, 0, z, bo64_, xo, nullptr, none, s_);
+        hop_half(lat_, gh64_, 0, k, 1.0, 0, xo, z, ax64_, nullptr, none, s_);  // (D x)_e
+        launch_residual(bp_, b64_, ax64_, ra, none, s_);
+        hop_half(lat_, gh64_, 1, k, 1.0, 0, z, xo, ax64_, nullptr, none, s_);  // (D x)_o
+        launch_residual(bp_, bo64_, ax64_, ra2, none, s_);
+        launch_norm(b64_, rb, s_);
+        launch_norm(bo64_, rb2, s_);
+        launch_export_half(z, x_, 0, lat_->g, s_);
+        launch_export_half(xo, x_, 1, lat_->g, s_);
     } else {
-        dslash(lat_, gauge64_, k, 0, x64_, t64_, nullptr, none, s_);
-        launch_residual(ax64_, b64_, t64_, ra, none, s_);  // |b - D x|^2
-        launch_norm(b64_, rb, s_);                          // |b|^2
-        launch_export(x64_, x_, lat_->g, s_);
+        const FieldRef dx = z.data == t64_.data ? r64_ : t64_;
+        dslash(lat_, gauge64_, k, 0, z, dx, nullptr, none, s_);
+        launch_residual(ax64_, b64_, dx, ra, none, s_);  // |b - D x|^2
+        launch_norm(b64_, rb, s_);                        // |b|^2
+        launch_export(z, x_, lat_->g, s_);
     }
     (void)hipMemcpyAsync(h_st_, st_, sizeof(RhsState) * p_.nrhs, hipMemcpyDeviceToHost, s_);
     (void)hipEventRecord(final_ev_, s_);

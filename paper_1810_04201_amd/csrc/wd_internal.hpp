@@ -144,6 +144,26 @@ __host__ __device__ inline Nbrs neighbours(const Geom &g, int i) {
     return n;
 }
 
+// Even-odd halves.  With an even brick x extent the two sites 2h and 2h+1
+// of the internal order differ only in x by one, so they have opposite
+// parity (x+y+z+t) mod 2.  A half field of parity p stores at entry h the
+// member of pair h with that parity; the half index of any site is its
+// internal index >> 1, so neighbours in a half field are found from the
+// full-lattice neighbour arithmetic.
+__host__ __device__ inline int site_of_half(const Geom &g, int h, int p) {
+    const int i0 = 2 * h;  // even x inside the brick (tx even), so x is even
+    const int ct = i0 / g.bvol, local = i0 - ct * g.bvol;
+    const int t = ct % g.L[3];
+    int col = ct / g.L[3];
+    col /= g.ncx;
+    const int by = col % g.ncy, bz = col / g.ncy;
+    const int q = local / g.tx;
+    const int y = by * g.ty + q % g.ty, z = bz * g.tz + q / g.ty;
+    return i0 + ((y + z + t + p) & 1);
+}
+
+inline bool eo_supported(const Geom &g) { return (g.tx & 1) == 0; }
+
 struct FieldRef {
     int prec;
     int nrhs;
@@ -230,6 +250,8 @@ enum RedMode {
     RED_B0 = 4,      // total = |b'|^2 -> rr0; start
     RED_AUX = 5,     // total -> aux
     RED_AUX2 = 6,    // total -> aux2
+    RED_AUX_ADD = 7, // aux += total
+    RED_AUX2_ADD = 8 // aux2 += total
 };
 
 struct RedArgs {
@@ -338,6 +360,7 @@ inline void choose_bricks(Geom &g) {
                 if (g.L[2] % c) continue;
                 const int v = a * b * c;
                 if (v % 64 || (v > 256 && !(v == 384 && big_ok))) continue;
+                if (a & 1) continue;  // even-odd halves pair x neighbours
                 const int faces = (a < g.L[0] ? 240 / a : 0) + (b < g.L[1] ? 240 / b : 0) +
                                   (c < g.L[2] ? 240 / c : 0);
                 const long long score = (a == g.L[0] ? (1LL << 40) : 0) + ((long long)v << 20) +
@@ -388,6 +411,21 @@ void launch_export(FieldRef f, double *canon, const Geom &g, hipStream_t s);
 // dst = src with a format conversion (same nrhs); gated rhs only
 void launch_convert(FieldRef src, FieldRef dst, Gate gate, hipStream_t s);
 void launch_zero(FieldRef f, hipStream_t s);
+// even-odd halves (V / 2 sites each, parity p): links of the parity-p sites
+// from the F64-18 tiles, in the half layout and format prec
+void launch_gauge_split(const void *g64, void *half, int prec, int p, const Geom &g,
+                        hipStream_t s);
+// canonical [rhs][V][12] float64 <-> half field of parity p (sites of the
+// other parity untouched on export)
+void launch_import_half(const double *canon, FieldRef f, int p, const Geom &g, hipStream_t s);
+void launch_export_half(FieldRef f, double *canon, int p, const Geom &g, hipStream_t s);
+// out_p = cs * c_p - k * H_{p,1-p} in_{1-p} on half fields (H the hopping
+// sum of Eq. (1), projectors exchanged for dagger; c.data == nullptr: no
+// c term), links gp of parity p and gq of parity 1 - p; red fuses |out|^2
+void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, double k,
+                     double cs, int dagger, FieldRef in, FieldRef c, FieldRef out,
+                     const RedArgs *red, Gate gate, hipStream_t s);
+
 // x64 += xlo ; xlo = 0: gate.mode GATE_TRIGGER for the rhs a reliable update
 // takes (with its batch test), otherwise every rhs that has not converged
 void launch_accum_zero(FieldRef x64, FieldRef xlo, Gate gate, hipStream_t s);

@@ -40,6 +40,15 @@ static int check(int Lx, int Ly, int Lz, int Lt) {
             }
             for (int s = 0; s < g.V; ++s)
                 if (seen[s] != 1) ++fails;
+            // even-odd halves: the parity-p member of pair h has half index h
+            if (wd::eo_supported(g))
+                for (int h = 0; h < g.V / 2; ++h)
+                    for (int p = 0; p < 2; ++p) {
+                        const int i = wd::site_of_half(g, h, p);
+                        int x, y, z, t;
+                        wd::coords_of(g, i, x, y, z, t);
+                        if ((i >> 1) != h || ((x + y + z + t) & 1) != p) ++fails;
+                    }
             // reduction partials: room for every reducing launch shape (a
             // launch writes index block * nrhs + rhs for each of its blocks
             // per rhs)
