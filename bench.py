@@ -250,6 +250,7 @@ def main():
         ex = {}
         ex.update(stencil_alone(wd, torch, lat, bd, V, kappa, stream))
         ex.update(other_mixed(args, lat, bd, kappa, stream, torch))
+        ex["even_odd"] = even_odd(args, wd, lat, bd, kappa, stream, torch, V)
         lat.close()
         del Ud
         torch.cuda.empty_cache()
@@ -379,6 +380,43 @@ def other_mixed(args, lat, bd, kappa, stream, torch):
     return {f"mixed_{other}_s": round(info[0]["seconds"], 3),
             f"mixed_{other}_iters": info[0]["iters"],
             f"mixed_{other}_true_rel_resid": info[0]["true_rel_resid"]}
+
+
+def even_odd(args, wd, lat, bd, kappa, stream, torch, V):
+    """The same system through the even-odd Schur complement (FP64 and mixed
+    FP16-12), with the half-field stencil's average launch time."""
+    res = {}
+    for prec in ("f64", args.mixed):
+        x = torch.zeros_like(bd)
+        wd.wd_timing_reset()
+        wd.wd_timing_enable(True)
+        with torch.cuda.stream(stream):
+            rc, info = lat.solve(bd, x, kappa, tol=args.tol, prec=prec, even_odd=True,
+                                 stream=stream)
+        torch.cuda.synchronize()
+        wd.wd_timing_enable(False)
+        ms, _ = wd.wd_timing_read("eo_" + prec)
+        it, up = info[0]["iters"], info[0]["reliable_updates"]
+        res[f"{prec}_s"] = round(info[0]["seconds"], 3)
+        res[f"{prec}_iters"] = it
+        res[f"{prec}_true_rel_resid"] = info[0]["true_rel_resid"]
+        res[f"{prec}_rel_resid_D"] = info[0]["rel_resid_D"]
+        # half-field launches that did work in this precision (gated launches
+        # that found nothing to do are timed too, so the average is an upper
+        # bound): 4 per inner iteration; in float64 also b^ and M^dag b^ (3),
+        # 4 per reliable update after the first, and the odd half and the
+        # final residual (3)
+        n = 4 * it if prec != "f64" else 4 * it + 3 + 4 * max(up - 1, 0) + 3
+        if n:
+            # one launch writes half the sites and reads every link once
+            # (forward links of its parity, backward of the other) and the
+            # other half's spinors; the c field some launches add is not counted
+            avg = ms / n
+            per_site = 8 * LINK_BYTES[prec] // 4 + 2 * SPINOR_BYTES[prec]
+            res[f"hop_{prec}_avg_ms"] = round(avg, 4)
+            res[f"hop_{prec}_GBps_algorithmic"] = round((V // 2) * per_site / avg / 1e6, 1)
+    log(f"even-odd: {res}")
+    return res
 
 
 def multi_rhs(np, torch, synth, wd):
