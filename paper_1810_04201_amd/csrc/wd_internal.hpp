@@ -288,15 +288,17 @@ constexpr int kTmMaxBlock = WD_TM_MAXB;
 
 inline bool tm_eligible(const Geom &g) { return g.bvol % 64 == 0 && g.bvol <= kTmMaxBlock; }
 
-// sites per marching workgroup: a contiguous part of a brick slice (whole
-// multiples of 64).  float64 takes up to 384 (one workgroup per CU holds its
+// sites per marching workgroup: a contiguous part of a brick slice (a
+// multiple of 64 dividing bvol).  float64 takes up to 384 (one workgroup per CU holds its
 // two LDS slice images); the float kernels run four waves per SIMD and do
 // best with at most 256.
 inline int tm_wvol(const Geom &g, int prec) {
     const int cap = prec == WD_F64 ? 384 : 256;
-    int w = g.bvol;
-    while (w > cap && w % 128 == 0) w /= 2;
-    return w;
+    if (g.bvol <= cap) return g.bvol;
+    // the largest multiple of 64 within the cap that divides the brick
+    for (int w = cap - cap % 64; w >= 64; w -= 64)
+        if (g.bvol % w == 0) return w;
+    return g.bvol;
 }
 
 // time slices per chunk: enough workgroups over all rhs to fill the chip (a
