@@ -17,7 +17,7 @@
  * Conventions shared by every call
  * --------------------------------
  * - Lattice extents dims[4] = {Lx, Ly, Lz, Lt}, each even and >= 2; V is
- *   their product; V * nrhs must stay below 2^31 / 12.
+ *   their product, at most 2^28.
  * - Site index s = x + Lx*(y + Ly*(z + Lz*t)); direction mu = 0,1,2,3 =
  *   x,y,z,t (the link arrays U_x..U_t of Sec. 6.2).
  * - Canonical gauge field (caller-owned, DEVICE memory, float64):

@@ -220,9 +220,10 @@ int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out
                         (int)dims[m]);
         V *= dims[m];
     }
-    if (V * 12 * 12 >= (int64_t)1 << 31)
-        return fail(WD_ERR_ARG, "volume %lld too large (V * 12 rhs * 12 must be < 2^31)",
-                    (long long)V);
+    // device index arithmetic is 32-bit over sites of one rhs (offsets up to
+    // a few V); byte offsets are 64-bit
+    if (V > ((int64_t)1 << 28))
+        return fail(WD_ERR_ARG, "volume %lld too large (at most 2^28 sites)", (long long)V);
     if (bc_flags & ~(uint32_t)(WD_BC_ANTIPERIODIC_T | WD_SIGN_PLUS_KAPPA))
         return fail(WD_ERR_ARG, "unknown lattice flags 0x%x", bc_flags);
     wd_lattice *lat = new (std::nothrow) wd_lattice();

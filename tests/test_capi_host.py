@@ -53,6 +53,19 @@ def test_plus_kappa_flag_accepted():
     assert wd.lib.wd_destroy_lattice(h) == wd.WD_OK
 
 
+def test_volume_limit():
+    # 64^3 x 64 (16.8 M sites) is accepted; beyond 2^28 sites is not
+    d = (ctypes.c_int32 * 4)(64, 64, 64, 64)
+    h = ctypes.c_void_p()
+    assert wd.lib.wd_create_lattice(d, 1, ctypes.byref(h)) == wd.WD_OK
+    v = ctypes.c_int64()
+    assert wd.lib.wd_lattice_volume(h, ctypes.byref(v)) == 0 and v.value == 64 ** 4
+    assert wd.lib.wd_destroy_lattice(h) == wd.WD_OK
+    d = (ctypes.c_int32 * 4)(256, 256, 64, 128)
+    assert wd.lib.wd_create_lattice(d, 1, ctypes.byref(h)) == wd.WD_ERR_ARG
+    assert "2^28" in wd.last_error()
+
+
 def test_bad_flags_and_null():
     d = (ctypes.c_int32 * 4)(4, 4, 4, 4)
     h = ctypes.c_void_p()
@@ -107,3 +120,27 @@ def test_no_unresolved_library_symbols():
                          text=True, check=True).stdout
     own = [line for line in out.splitlines() if "_ZN2wd" in line or " wd_" in line]
     assert not own, own
+
+
+def test_even_odd_needs_even_x_bricks(monkeypatch):
+    # an odd brick x extent (forced) cannot pair x neighbours into halves:
+    # refused before any device work, for the solve and the Schur operator
+    monkeypatch.setenv("WD_BRICK", "3,4,4")
+    lat = wd.Lattice((6, 4, 4, 4))
+    infos = (wd.wd_solve_info * 1)()
+    p = wd.make_params(0.12, even_odd=True)
+    a, b = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    assert wd.lib.wd_cg_solve(lat.handle, ctypes.byref(p), a, b, infos, None) == wd.WD_ERR_ARG
+    assert "even x extent" in wd.last_error()
+    assert wd.lib.wd_apply_schur(lat.handle, 0.12, 0, 0, 1, a, b, None) == wd.WD_ERR_ARG
+    lat.close()
+
+
+def test_bad_form_flags_rejected():
+    lat = wd.Lattice((4, 4, 4, 4))
+    infos = (wd.wd_solve_info * 1)()
+    a, b = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    for form in (2, 1 << 9, wd.WD_SOLVE_EVEN_ODD | 3):
+        p = wd.make_params(0.12, form=form)
+        assert wd.lib.wd_cg_solve(lat.handle, ctypes.byref(p), a, b, infos, None) == wd.WD_ERR_ARG
+    lat.close()
