@@ -254,6 +254,7 @@ def main():
         lat.close()
         del Ud
         torch.cuda.empty_cache()
+        ex["slab_share"] = slab_share(np, torch, synth, wd)
         ex["small_configs"] = small_configs(np, torch, synth, wd)
         ex["multi_rhs"] = multi_rhs(np, torch, synth, wd)
         ex["serving"] = serving(np, torch, synth, wd, args.serve_requests)
@@ -287,6 +288,57 @@ def copy_bandwidth(torch):
     gbs = 2 * n * 8 / statistics.median(ts) / 1e6
     log(f"copy: {gbs:.0f} GB/s")
     return gbs
+
+
+def slab_share(np, torch, synth, wd):
+    """One GPU's share of 48^3 x 96 cut into 8 t-slabs (48^3 x 12, slab 0 of
+    the seed-3 configuration): the plain stencil on the slab against the
+    halo path (faces packed, staged and read across the slab ends; the slab
+    receives its own faces in place of its neighbours').  The transfer time
+    of a face over one xGMI link (~153 GB/s) is an estimate, not measured."""
+    dev = torch.device("cuda:0")
+    full = (48, 48, 48, 96)
+    dims = (48, 48, 48, 12)
+    V = int(np.prod(dims))
+    vs = 48 ** 3
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.gauge(full, 3, synth.EXP, 0.3, t0=0, t1=12)).to(dev))
+    up = synth.gauge(full, 3, synth.EXP, 0.3, t0=95, t1=96)[:, 3]
+    wd.wd_set_halo_gauge(lat, torch.from_numpy(np.ascontiguousarray(up)).to(dev))
+    psi = torch.from_numpy(synth.gaussian_spinor(dims, 103)).to(dev)
+    fa, fb = wd.Field(lat, "f64"), wd.Field(lat, "f64")
+    fa.load(psi)
+    n = wd.face_numel(lat)
+    sp = torch.empty(n, dtype=torch.float64, device=dev)
+    sn = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def timeit(fn, reps=20):
+        for _ in range(3):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    plain = timeit(lambda: wd.wd_dslash(lat, 0.1245, 0, fa, fb))
+    pack = timeit(lambda: wd.wd_halo_pack(lat, fa, sp, sn))
+    halo = timeit(lambda: wd.wd_dslash_halo(lat, 0.1245, fa, fb, sn, sp, False, False))
+    face_bytes = n * 8
+    res = {"lattice": "48x48x48x12 (one of 8 t-slabs of 48x48x48x96)",
+           "dslash_plain_ms": round(plain, 4), "halo_pack_ms": round(pack, 4),
+           "dslash_halo_ms": round(halo, 4),
+           "dslash_halo_GBps_algorithmic": round(V * BYTES_PER_SITE["f64"] / halo / 1e6, 1),
+           "face_bytes_per_direction": face_bytes,
+           "face_over_xgmi_link_us_estimate": round(face_bytes / 153e9 * 1e6, 1)}
+    fa.close()
+    fb.close()
+    lat.close()
+    log(f"slab share: {res}")
+    return res
 
 
 def small_configs(np, torch, synth, wd):

@@ -164,6 +164,38 @@ int wd_field_export(const wd_field *f, double *canon, void *stream);
 int wd_dslash(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_field *out,
               void *stream);
 
+/* ------------------------------------------------------- halo exchange
+ * A lattice may be one t-slab of a larger lattice cut along t over several
+ * GPUs (one process per GPU, slab r holding global t in [r Lt, (r+1) Lt)).
+ * Its stencil then takes the t hops across the slab ends from faces that
+ * the neighbouring slabs pack, instead of wrapping around:
+ *   wd_set_halo_gauge  once per gauge field: U_t(x, -1), the t links that
+ *                      enter this slab from the previous one (the previous
+ *                      slab's U_t on its last slice), canonical float64
+ *                      device array [Lx*Ly*Lz][3][3][2] (x fastest).
+ *   wd_halo_pack       writes this slab's two faces: send_prev goes to the
+ *                      previous slab, send_next to the next one.
+ *   wd_dslash_halo     out = D in (dagger 0) or D^dag in (dagger 1) on the
+ *                      slab, with recv_prev / recv_next the faces received
+ *                      from the previous / next slab (packed with the same
+ *                      dagger).  WD_HALO_FIRST / WD_HALO_LAST: this slab holds
+ *                      global t = 0 / t = T-1, where the antiperiodic sign
+ *                      applies.  A single slab with its own faces and
+ *                      WD_HALO_FIRST | WD_HALO_LAST is the whole lattice.
+ * Faces (device, caller-owned): per rhs 6 planes of V/Lt complex float64 (the
+ * projected half-spinor of a boundary slice, 96 bytes per face site), sites
+ * in the library's internal face order, the same on every slab of one shape.
+ * Float64 fields; lattices whose bricks are whole multiples of 64 sites (the
+ * marching stencil).  Stream-ordered; wd_dslash_halo allocates its staging
+ * stream-ordered. */
+enum { WD_HALO_FIRST = 1u << 0, WD_HALO_LAST = 1u << 1 };
+int wd_set_halo_gauge(wd_lattice *lat, const double *U_prev, void *stream);
+int wd_halo_pack(wd_lattice *lat, int dagger, const wd_field *in, double *send_prev,
+                 double *send_next, void *stream);
+int wd_dslash_halo(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_field *out,
+                   const double *recv_prev, const double *recv_next, uint32_t flags,
+                   void *stream);
+
 /* ---------------------------------------------------------------- solver */
 
 typedef struct {

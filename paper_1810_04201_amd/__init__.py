@@ -41,6 +41,7 @@ WD_BC_ANTIPERIODIC_T = 1
 WD_SIGN_PLUS_KAPPA = 2
 WD_FORM_CGNR, WD_FORM_CGNE = 0, 1
 WD_SOLVE_EVEN_ODD = 1 << 8
+WD_HALO_FIRST, WD_HALO_LAST = 1, 2
 FORM = {"cgnr": WD_FORM_CGNR, "cgne": WD_FORM_CGNE, WD_FORM_CGNR: WD_FORM_CGNR,
         WD_FORM_CGNE: WD_FORM_CGNE}
 
@@ -89,6 +90,9 @@ _SIGS = {
     "wd_apply_Ddag": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp],
     "wd_apply": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
     "wd_apply_schur": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
+    "wd_set_halo_gauge": [_vp, _vp, _vp],
+    "wd_halo_pack": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "wd_dslash_halo": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp],
     "wd_field_create": [_vp, _i32, _i32, ctypes.POINTER(_vp)],
     "wd_field_destroy": [_vp],
     "wd_field_import": [_vp, _vp, _vp],
@@ -208,6 +212,32 @@ def wd_apply_schur(h, kappa, prec, dagger, nrhs, inp, out, volume, stream=None):
     n = volume * 24 * nrhs
     _check(lib.wd_apply_schur(h, float(kappa), PREC[prec], int(dagger), int(nrhs),
                               _dptr(inp, n, "in"), _dptr(out, n, "out"), _stream(stream)))
+
+
+def face_numel(lattice, nrhs=1):
+    """float64 elements of one halo face buffer (96 bytes per face site)."""
+    return nrhs * 12 * (lattice.volume // lattice.dims[3])
+
+
+def wd_set_halo_gauge(lattice, U_prev, stream=None):
+    n = 18 * (lattice.volume // lattice.dims[3])
+    _check(lib.wd_set_halo_gauge(lattice.handle, _dptr(U_prev, n, "U_prev"), _stream(stream)))
+
+
+def wd_halo_pack(lattice, field, send_prev, send_next, dagger=False, stream=None):
+    n = face_numel(lattice, field.nrhs)
+    _check(lib.wd_halo_pack(lattice.handle, 1 if dagger else 0, field.handle,
+                            _dptr(send_prev, n, "send_prev"), _dptr(send_next, n, "send_next"),
+                            _stream(stream)))
+
+
+def wd_dslash_halo(lattice, kappa, fin, fout, recv_prev, recv_next, first, last, dagger=False,
+                   stream=None):
+    n = face_numel(lattice, fin.nrhs)
+    flags = (WD_HALO_FIRST if first else 0) | (WD_HALO_LAST if last else 0)
+    _check(lib.wd_dslash_halo(lattice.handle, float(kappa), 1 if dagger else 0, fin.handle,
+                              fout.handle, _dptr(recv_prev, n, "recv_prev"),
+                              _dptr(recv_next, n, "recv_next"), flags, _stream(stream)))
 
 
 def wd_apply_D(h, kappa, prec, inp, out, volume, stream=None):

@@ -318,11 +318,15 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
 // of a column run side by side and read its links from L2 after the first.
 // The fused reduction writes one partial per (column, slice, part, rhs), so
 // its summation order does not depend on the chunk length or on nrhs.
-template <int PREC, bool DAG, bool RED, int GROUP>
+// HALO: the lattice is one t-slab of a larger one; the t hops across its
+// ends read staged faces (see Halo) in place of the wrapped slices: only the
+// sources of the prologue's spinor and link, of the last step's slice copy,
+// and the boundary sign change.
+template <int PREC, bool DAG, bool RED, int GROUP, bool HALO = false>
 __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *__restrict__ gauge,
                                                    FieldRef in, FieldRef out, double kappa_d,
                                                    RedArgs red, Gate gate, int tchunk,
-                                                   int ncols) {
+                                                   int ncols, Halo halo) {
     using R = typename Spinor<PREC>::R;
     extern __shared__ __align__(16) char lds[];
     __shared__ double wsum[kTmMaxBlock / 64];
@@ -352,6 +356,20 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
     constexpr int SB = -SF;
     const R kappa = (R)kappa_d;
 
+    // halo: this workgroup's part of a face (first face site, staged views)
+    const int fbase = col * bvol + h * wvol;
+    FieldRef hprev = fin, hnext = fin;
+    if (HALO) {
+        hprev.data = (void *)halo.prev;
+        hnext.data = (void *)halo.next;
+        const int vf = g.V / Lt;
+        hprev.V = hnext.V = vf;
+        hprev.stride = hnext.stride = rhs_stride(vf);
+        hprev = rhs_view(hprev, rhs);
+        hnext = rhs_view(hnext, rhs);
+    }
+    const bool prev_from_halo = HALO && t0 == 0;
+
     // prologue: slice t0 into image 0, and the backward t hop from t0 - 1
     slice_copy<PREC>(fin, (cbase + t0 * bvol) >> 6, img0);
     cx<R> cw0[3], cw1[3];
@@ -359,17 +377,18 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
         const int tprev = t0 == 0 ? Lt - 1 : t0 - 1;
         const int ip = cbase + tprev * bvol + l;
         cx<R> p[12];
-        Spinor<PREC>::load(fin, ip, p);
+        Spinor<PREC>::load(prev_from_halo ? hprev : fin, prev_from_halo ? fbase + l : ip, p);
         cx<R> h0[3], h1[3];
         project<3, SB>(p, h0, h1);
-        const R sg = (g.antiperiodic && t0 == 0) ? R(-1) : R(1);
+        const R sg = (g.antiperiodic && t0 == 0 && (!HALO || halo.first)) ? R(-1) : R(1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             h0[c] = scale(sg, h0[c]);
             h1[c] = scale(sg, h1[c]);
         }
         cx<R> u[9];
-        Link<PREC>::load(gauge, 3, ip, u);
+        Link<PREC>::load(prev_from_halo ? halo.links : gauge, 3, prev_from_halo ? fbase + l : ip,
+                         u);
         su3_mul<true>(u, h0, cw0);
         su3_mul<true>(u, h1, cw1);
     }
@@ -380,7 +399,10 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
         const FieldRef cur = lds_view(fin, odd ? img1 : img0);
         const FieldRef nxt = lds_view(fin, odd ? img0 : img1);
         const int tn = t + 1 < Lt ? t + 1 : 0;
-        slice_copy<PREC>(fin, (cbase + tn * bvol) >> 6, (char *)nxt.data);
+        // the slice after the slab's last one is the staged next face
+        const bool next_from_halo = HALO && t + 1 == Lt;
+        slice_copy<PREC>(next_from_halo ? hnext : fin,
+                         next_from_halo ? fbase >> 6 : (cbase + tn * bvol) >> 6, (char *)nxt.data);
         const int sbase = cbase + t * bvol;
         const int i = sbase + l;
         const Nbrs nb = neighbours(g, i);
@@ -410,7 +432,8 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
         {
             cx<R> nx[12];
             Spinor<PREC>::load(nxt, l, nx);
-            hop_p<3, SF, false>(nx, ut, g.antiperiodic && t == Lt - 1, acc);
+            hop_p<3, SF, false>(nx, ut, g.antiperiodic && t == Lt - 1 && (!HALO || halo.last),
+                                acc);
         }
         accumulate<3, SB>(cw0, cw1, acc);
         cx<R> c[12];
@@ -494,7 +517,8 @@ static void launch_tm_k(dim3 grid, dim3 bs, size_t lds, hipStream_t s, const Geo
     constexpr int G = HopGroup<PREC>::value;
     auto k = k_dslash_tm<PREC, DAG, RED, G>;
     allow_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+    hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols,
+                       Halo{nullptr, nullptr, nullptr, 0, 0});
 }
 
 template <int PREC>
@@ -673,6 +697,128 @@ void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, doubl
         case WD_F64: launch_hop_half_prec<WD_F64>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
         case WD_F32: launch_hop_half_prec<WD_F32>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
         default: launch_hop_half_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
+    }
+}
+
+// ------------------------------------------------------------------ halo exchange
+
+// Faces of a t-slab for its neighbours (float64, wire format): one lane per
+// face site and rhs.  to_prev: (1 + SF gamma_t) psi(x, 0), the projection
+// the previous slab's forward t hop applies; to_next: (1 + SB gamma_t)
+// psi(x, Lt-1) for the next slab's backward t hop (which multiplies it by
+// U_t(x, Lt-1)^dag, a link the next slab holds as its entering links).
+template <bool DAG>
+__global__ void __launch_bounds__(256) k_halo_pack(Geom g, FieldRef in, double2 *__restrict__ to_prev,
+                                                   double2 *__restrict__ to_next) {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const int Lt = g.L[3];
+    const int vf = g.V / Lt;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= vf) return;
+    const int rhs = blockIdx.y;
+    const FieldRef fin = rhs_view(in, rhs);
+    const int col = f / g.bvol, loc = f - col * g.bvol;
+    const int i0 = col * Lt * g.bvol + loc;  // slice 0
+    const int il = i0 + (Lt - 1) * g.bvol;   // slice Lt - 1
+    const size_t fofs = (size_t)rhs * 6 * vf;
+    cx<double> p[12], h0[3], h1[3];
+    Spinor<WD_F64>::load(fin, i0, p);
+    project<3, SF>(p, h0, h1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        to_prev[fofs + (size_t)c * vf + f] = make_double2(h0[c].re, h0[c].im);
+        to_prev[fofs + (size_t)(3 + c) * vf + f] = make_double2(h1[c].re, h1[c].im);
+    }
+    Spinor<WD_F64>::load(fin, il, p);
+    project<3, SB>(p, h0, h1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        to_next[fofs + (size_t)c * vf + f] = make_double2(h0[c].re, h0[c].im);
+        to_next[fofs + (size_t)(3 + c) * vf + f] = make_double2(h1[c].re, h1[c].im);
+    }
+}
+
+void launch_halo_pack(const Geom &g, int dagger, FieldRef in, double *to_prev, double *to_next,
+                      hipStream_t s) {
+    const dim3 grid(blocks_for(g.V / g.L[3], 256), in.nrhs), bs(256);
+    if (dagger)
+        hipLaunchKernelGGL(k_halo_pack<true>, grid, bs, 0, s, g, in, (double2 *)to_prev,
+                           (double2 *)to_next);
+    else
+        hipLaunchKernelGGL(k_halo_pack<false>, grid, bs, 0, s, g, in, (double2 *)to_prev,
+                           (double2 *)to_next);
+}
+
+// wire-format face -> spinor tiles: spins 0, 1 = the half-spinor, spins 2, 3
+// zero (the t projectors then return the half-spinor exactly)
+__global__ void __launch_bounds__(256) k_halo_stage(const double2 *__restrict__ wire, FieldRef st,
+                                                    int vf) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= vf) return;
+    const int rhs = blockIdx.y;
+    const size_t fofs = (size_t)rhs * 6 * vf;
+    cx<double> v[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double2 d = wire[fofs + (size_t)k * vf + f];
+        v[k] = {d.x, d.y};
+        v[6 + k] = {0.0, 0.0};
+    }
+    Spinor<WD_F64>::store(rhs_view(st, rhs), f, v);
+}
+
+void launch_halo_stage(const Geom &g, const double *wire, FieldRef staged, hipStream_t s) {
+    const int vf = g.V / g.L[3];
+    hipLaunchKernelGGL(k_halo_stage, dim3(blocks_for(vf, 256), staged.nrhs), dim3(256), 0, s,
+                       (const double2 *)wire, staged, vf);
+}
+
+// canonical U_t(x, -1) over the (x, y, z) of a face -> gauge tiles over face
+// sites (mu = 3 planes; the others are not read)
+__global__ void __launch_bounds__(256) k_halo_links(Geom g, const double2 *__restrict__ canon,
+                                                    void *__restrict__ links) {
+    const int vf = g.V / g.L[3];
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= vf) return;
+    const int col = f / g.bvol, loc = f - col * g.bvol;
+    int x, y, z, t;
+    coords_of(g, col * g.L[3] * g.bvol + loc, x, y, z, t);
+    const double2 *src = canon + (size_t)(x + g.L[0] * (y + g.L[1] * z)) * 9;
+    cx<double> u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = {src[k].x, src[k].y};
+    Link<WD_F64>::store(links, 3, f, u);
+}
+
+void launch_halo_links(const Geom &g, const double *canon, void *links, hipStream_t s) {
+    const int vf = g.V / g.L[3];
+    hipLaunchKernelGGL(k_halo_links, dim3(blocks_for(vf, 256)), dim3(256), 0, s, g,
+                       (const double2 *)canon, links);
+}
+
+bool halo_supported(const Geom &g) { return tm_eligible(g) && tm_fits<WD_F64>(g); }
+
+void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
+                        FieldRef out, const Halo &halo, hipStream_t s) {
+    const int wvol = tm_wvol(g, WD_F64);
+    const int nsub = g.bvol / wvol;
+    const int tch = tm_chunk(g, in.nrhs * nsub);
+    const int ncols = g.V / (g.L[3] * g.bvol);
+    const dim3 grid(tm_blocks(g, tch) * nsub * in.nrhs), bs(wvol);
+    const size_t lds = 2 * slice_bytes<WD_F64>(wvol);
+    constexpr int G = HopGroup<WD_F64>::value;
+    const Gate none{nullptr, nullptr, GATE_ACTIVE};
+    if (dagger) {
+        auto k = k_dslash_tm<WD_F64, true, false, G, true>;
+        allow_lds(k, lds);
+        hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, RedArgs{}, none, tch,
+                           ncols, halo);
+    } else {
+        auto k = k_dslash_tm<WD_F64, false, false, G, true>;
+        allow_lds(k, lds);
+        hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, RedArgs{}, none, tch,
+                           ncols, halo);
     }
 }
 

@@ -154,15 +154,13 @@ static void drain_pending_locked() {
     g_pending.clear();
 }
 
-void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
-            const FieldRef &out, const RedArgs *red, Gate gate, hipStream_t s) {
-    // the kernels compute in - kappa' * (hops): the +kappa sign is kappa' = -kappa
-    kappa = -lat->hop_sign * kappa;
+// a stencil launch, bracketed by events on its stream while timing is on
+template <typename F>
+static void timed(const char *name, hipStream_t s, F &&launch) {
     if (!g_timing.load(std::memory_order_relaxed)) {
-        launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s);
+        launch();
         return;
     }
-    static const char *names[3] = {"dslash_f64", "dslash_f32", "dslash_f16"};
     hipEvent_t a, b;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
@@ -171,10 +169,19 @@ void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const 
         b = take_event();
     }
     (void)hipEventRecord(a, s);
-    launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s);
+    launch();
     (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(g_tmu);
-    g_pending.push_back({names[in.prec], a, b});
+    g_pending.push_back({name, a, b});
+}
+
+void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
+            const FieldRef &out, const RedArgs *red, Gate gate, hipStream_t s) {
+    // the kernels compute in - kappa' * (hops): the +kappa sign is kappa' = -kappa
+    kappa = -lat->hop_sign * kappa;
+    static const char *names[3] = {"dslash_f64", "dslash_f32", "dslash_f16"};
+    timed(names[in.prec], s,
+          [&] { launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s); });
 }
 
 void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
@@ -182,23 +189,10 @@ void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs
               Gate gate, hipStream_t s) {
     // D_{p,1-p} = hop_sign * kappa * H_{p,1-p}; the kernel computes cs c - k H in
     const double k = -lat->hop_sign * kappa;
-    if (!g_timing.load(std::memory_order_relaxed)) {
-        launch_hop_half(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, out, red, gate, s);
-        return;
-    }
     static const char *names[3] = {"eo_f64", "eo_f32", "eo_f16"};
-    hipEvent_t a, b;
-    {
-        std::lock_guard<std::mutex> lk(g_tmu);
-        if (g_pending.size() > 4096) drain_pending_locked();
-        a = take_event();
-        b = take_event();
-    }
-    (void)hipEventRecord(a, s);
-    launch_hop_half(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, out, red, gate, s);
-    (void)hipEventRecord(b, s);
-    std::lock_guard<std::mutex> lk(g_tmu);
-    g_pending.push_back({names[in.prec], a, b});
+    timed(names[in.prec], s, [&] {
+        launch_hop_half(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, out, red, gate, s);
+    });
 }
 
 }  // namespace wd
@@ -246,6 +240,7 @@ int wd_destroy_lattice(wd_lattice *lat) {
         for (int q = 0; q < 2; ++q)
             if (lat->gauge_eo[p][q]) (void)hipFree(lat->gauge_eo[p][q]);
     }
+    if (lat->halo_links) (void)hipFree(lat->halo_links);
     delete lat;
     return WD_OK;
 }
@@ -263,6 +258,7 @@ int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes) {
         if (lat->gauge[p]) b += gauge_bytes(p, lat->g.V);
         if (lat->gauge_eo[p][0]) b += 2 * gauge_bytes(p, lat->g.V / 2);
     }
+    if (lat->halo_links) b += gauge_bytes(WD_F64, lat->g.V / lat->g.L[3]);
     *bytes = b;
     return WD_OK;
 }
@@ -430,6 +426,80 @@ int wd_apply_schur(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs
     launch_export_half(oe, out, 0, lat->g, s);
     launch_zero(to, s);
     launch_export_half(to, out, 1, lat->g, s);  // odd sites of out = 0
+    (void)hipFreeAsync(mem, s);
+    WD_LAUNCH_CHECK();
+    return WD_OK;
+}
+
+int wd_set_halo_gauge(wd_lattice *lat, const double *U_prev, void *stream) {
+    if (!lat || !U_prev) return fail(WD_ERR_ARG, "null argument");
+    if (!halo_supported(lat->g))
+        return fail(WD_ERR_ARG, "halo exchange needs the marching stencil (bricks of a multiple "
+                                "of 64 sites)");
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(lat->mu);
+    if (!lat->halo_links) {
+        void *p = nullptr;
+        if (hipMalloc(&p, gauge_bytes(WD_F64, lat->g.V / lat->g.L[3])) != hipSuccess)
+            return fail(WD_ERR_NOMEM, "hipMalloc of the halo links failed");
+        lat->halo_links = p;
+    }
+    launch_halo_links(lat->g, U_prev, lat->halo_links, s);
+    WD_LAUNCH_CHECK();
+    WD_HIP_CHECK(hipStreamSynchronize(s));
+    return WD_OK;
+}
+
+int wd_halo_pack(wd_lattice *lat, int dagger, const wd_field *in, double *send_prev,
+                 double *send_next, void *stream) {
+    if (!lat || !in || !send_prev || !send_next) return fail(WD_ERR_ARG, "null argument");
+    if (in->lat != lat) return fail(WD_ERR_ARG, "field of another lattice");
+    if (in->prec != WD_F64) return fail(WD_ERR_ARG, "halo exchange is float64");
+    if (dagger != 0 && dagger != 1) return fail(WD_ERR_ARG, "dagger must be 0 or 1");
+    if (send_prev == send_next) return fail(WD_ERR_ARG, "the two faces must not overlap");
+    launch_halo_pack(lat->g, dagger, in->ref, send_prev, send_next, (hipStream_t)stream);
+    WD_LAUNCH_CHECK();
+    return WD_OK;
+}
+
+int wd_dslash_halo(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_field *out,
+                   const double *recv_prev, const double *recv_next, uint32_t flags,
+                   void *stream) {
+    if (!lat || !in || !out || !recv_prev || !recv_next) return fail(WD_ERR_ARG, "null argument");
+    if (in == out) return fail(WD_ERR_ARG, "in and out must be different fields");
+    if (in->lat != lat || out->lat != lat) return fail(WD_ERR_ARG, "fields of another lattice");
+    if (in->prec != WD_F64 || out->prec != WD_F64)
+        return fail(WD_ERR_ARG, "halo exchange is float64");
+    if (in->nrhs != out->nrhs) return fail(WD_ERR_ARG, "in/out nrhs differ");
+    if (!std::isfinite(kappa)) return fail(WD_ERR_ARG, "kappa not finite");
+    if (dagger != 0 && dagger != 1) return fail(WD_ERR_ARG, "dagger must be 0 or 1");
+    if (flags & ~(uint32_t)(WD_HALO_FIRST | WD_HALO_LAST))
+        return fail(WD_ERR_ARG, "unknown halo flags 0x%x", flags);
+    if (!halo_supported(lat->g))
+        return fail(WD_ERR_ARG, "halo exchange needs the marching stencil (bricks of a multiple "
+                                "of 64 sites)");
+    if (!lat->has_gauge) return fail(WD_ERR_NOGAUGE, "gauge field not set");
+    if (!lat->halo_links) return fail(WD_ERR_STATE, "halo links not set (wd_set_halo_gauge)");
+    hipStream_t s = (hipStream_t)stream;
+    const int vf = lat->g.V / lat->g.L[3];
+    const size_t one = field_data_bytes(WD_F64, vf, in->nrhs) + 256;
+    void *mem = nullptr;
+    hipError_t he = hipMallocAsync(&mem, 2 * one, s);
+    if (he != hipSuccess)
+        return fail(WD_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s", 2 * one,
+                    hipGetErrorString(he));
+    char *cur = (char *)mem;
+    FieldRef sp = carve(cur, WD_F64, in->nrhs, vf);
+    cur = (char *)mem + one;
+    FieldRef sn = carve(cur, WD_F64, in->nrhs, vf);
+    launch_halo_stage(lat->g, recv_prev, sp, s);
+    launch_halo_stage(lat->g, recv_next, sn, s);
+    const Halo halo{sp.data, sn.data, lat->halo_links, (flags & WD_HALO_FIRST) ? 1 : 0,
+                    (flags & WD_HALO_LAST) ? 1 : 0};
+    const double k = -lat->hop_sign * kappa;
+    timed("halo_f64", s, [&] {
+        launch_dslash_halo(lat->g, lat->gauge[WD_F64], k, dagger, in->ref, out->ref, halo, s);
+    });
     (void)hipFreeAsync(mem, s);
     WD_LAUNCH_CHECK();
     return WD_OK;

@@ -16,6 +16,7 @@ struct wd_lattice {
     wd::Geom g{};
     void *gauge[3] = {nullptr, nullptr, nullptr};  // F64-18, F32-12, F16-12
     void *gauge_eo[3][2] = {};                     // even-odd halves [prec][parity]
+    void *halo_links = nullptr;                    // U_t(x, -1) over face sites (t-slab)
     bool has_gauge = false;
     double hop_sign = -1.0;  // D = 1 + hop_sign * kappa * (hops); kernels take 1 - kappa' H
     std::mutex mu;

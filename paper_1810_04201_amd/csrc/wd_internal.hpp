@@ -52,7 +52,7 @@ namespace wd {
 constexpr int kNComp = 12;  // 4 spins x 3 colours
 constexpr int kTile = 64;   // entries per tile
 
-inline size_t tiles_of(int64_t n) { return (size_t)((n + kTile - 1) / kTile); }
+__host__ __device__ inline size_t tiles_of(int64_t n) { return (size_t)((n + kTile - 1) / kTile); }
 
 __host__ __device__ inline size_t spinor_tile_bytes(int prec) {
     return prec == WD_F64 ? 12u * 1024u : (prec == WD_F32 ? 6u * 1024u : 3u * 1024u + 256u);
@@ -172,7 +172,7 @@ struct FieldRef {
     void *data;  // tiles
 };
 
-inline int rhs_stride(int V) { return (int)(tiles_of(V) * kTile); }
+__host__ __device__ inline int rhs_stride(int V) { return (int)(tiles_of(V) * kTile); }
 
 // bytes of a field of nrhs right-hand sides on V sites
 inline size_t field_data_bytes(int prec, int V, int nrhs) {
@@ -231,6 +231,26 @@ struct Gate {
     const RhsState *st;
     const BatchState *batch;
     int mode;
+};
+
+// Halo exchange for a lattice that is one t-slab of a larger one (one slab
+// per GPU).  Face site f = column * bvol + local site of a brick slice
+// (V / Lt of them, the same order on every slab of the same shape).  On the
+// wire a face is the projected half-spinor (1 +- gamma_t) psi of a boundary
+// slice: per rhs 6 planes of V / Lt double2, element ((rhs * 6 + k) * (V / Lt)
+// + f).  The receiver expands it into spinor tiles whose spins 0 and 1 hold
+// the half-spinor and spins 2 and 3 are zero, which the t projector maps
+// back to the same half-spinor exactly, so the stencil's code reads a staged
+// face like a slice:
+//   prev / next: staged faces (float64 spinor tiles of V / Lt sites, nrhs)
+//   links:       U_t(x, -1), the links entering from the previous slab
+//                (float64 gauge tiles of V / Lt sites, mu = 3 planes)
+//   first, last: this slab holds global t = 0 / t = T - 1 (antiperiodic sign)
+struct Halo {
+    const void *prev;
+    const void *next;
+    const void *links;
+    int first, last;
 };
 
 struct SolveCtl {
@@ -427,6 +447,20 @@ void launch_export_half(FieldRef f, double *canon, int p, const Geom &g, hipStre
 void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, double k,
                      double cs, int dagger, FieldRef in, FieldRef c, FieldRef out,
                      const RedArgs *red, Gate gate, hipStream_t s);
+
+// halo exchange (float64): the two faces of in for the neighbouring slabs
+// (to_prev: (1 -+ gamma_t) psi(x, 0) for its forward hop; to_next: the
+// backward projection of psi(x, Lt-1)), wire format
+void launch_halo_pack(const Geom &g, int dagger, FieldRef in, double *to_prev, double *to_next,
+                      hipStream_t s);
+// wire-format face -> staged face (spinor tiles of V / Lt sites)
+void launch_halo_stage(const Geom &g, const double *wire, FieldRef staged, hipStream_t s);
+// canonical U_t(x, -1) [Lx*Ly*Lz][3][3][2] -> gauge tiles over face sites
+void launch_halo_links(const Geom &g, const double *canon, void *links, hipStream_t s);
+// the marching stencil with t hops across the slab ends from staged faces
+bool halo_supported(const Geom &g);
+void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
+                        FieldRef out, const Halo &halo, hipStream_t s);
 
 // x64 += xlo ; xlo = 0: gate.mode GATE_TRIGGER for the rhs a reliable update
 // takes (with its batch test), otherwise every rhs that has not converged

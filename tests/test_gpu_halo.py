@@ -1,0 +1,131 @@
+"""Halo exchange across t-slabs (the single-GPU half of the sharded design).
+
+A lattice cut into slabs along t, each slab its own wd_lattice holding its
+part of the gauge and spinor fields; faces packed by wd_halo_pack are handed
+to the neighbouring slabs (here by passing the buffers: the transfer a
+multi-GPU run does over xGMI), and wd_dslash_halo on every slab must give
+the global stencil: against the oracle, and bit for bit against the plain
+stencil for a single slab that receives its own faces.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import wilson
+from gpu_util import gauge, site_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_1810_04201_amd as wd
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0"), wd
+
+
+def _slabs(env, dims, U, psis, nslab, kappa, dagger):
+    """D (or D^dag) of the global lattice computed slab by slab."""
+    torch, dev, wd = env
+    lx, ly, lz, lt = dims
+    lts = lt // nslab
+    vs = lx * ly * lz
+    nrhs = psis.shape[0]
+    lats, fins, fouts = [], [], []
+    for r in range(nslab):
+        sl = slice(r * lts * vs, (r + 1) * lts * vs)
+        lat = wd.Lattice((lx, ly, lz, lts))
+        lat.set_gauge(torch.from_numpy(np.ascontiguousarray(U[sl])).to(dev))
+        # links entering from the previous slab: its U_t on its last slice
+        tprev = (r * lts - 1) % lt
+        up = np.ascontiguousarray(U[tprev * vs:(tprev + 1) * vs, 3])
+        wd.wd_set_halo_gauge(lat, torch.from_numpy(up).to(dev))
+        fi = wd.Field(lat, "f64", nrhs=nrhs)
+        fi.load(torch.from_numpy(np.ascontiguousarray(psis[:, sl])).to(dev).squeeze(0)
+                if nrhs == 1 else torch.from_numpy(np.ascontiguousarray(psis[:, sl])).to(dev))
+        lats.append(lat)
+        fins.append(fi)
+        fouts.append(wd.Field(lat, "f64", nrhs=nrhs))
+    n = wd.face_numel(lats[0], nrhs)
+    to_prev = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(nslab)]
+    to_next = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(nslab)]
+    for r in range(nslab):
+        wd.wd_halo_pack(lats[r], fins[r], to_prev[r], to_next[r], dagger=dagger)
+    out = []
+    for r in range(nslab):
+        # from the previous slab: what it sent to its next; from the next: its to_prev
+        wd.wd_dslash_halo(lats[r], kappa, fins[r], fouts[r], to_next[(r - 1) % nslab],
+                          to_prev[(r + 1) % nslab], first=(r == 0), last=(r == nslab - 1),
+                          dagger=dagger)
+        o = torch.empty((nrhs, lts * vs, 4, 3, 2), dtype=torch.float64, device=dev)
+        fouts[r].store(o if nrhs > 1 else o[0])
+        out.append(o)
+    torch.cuda.synchronize()
+    res = torch.cat(out, dim=1).cpu().numpy()
+    for f in fins + fouts:
+        f.close()
+    for lat in lats:
+        lat.close()
+    return res
+
+
+@pytest.mark.parametrize("dims,nslab", [((4, 4, 4, 8), 2), ((8, 8, 8, 16), 4), ((8, 4, 8, 12), 3)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_slabs_equal_global_stencil(env, dims, nslab, dagger):
+    print(f"halo dims={dims} slabs={nslab} dagger={dagger}", flush=True)
+    U = gauge(dims, 111)
+    psi = synth.gaussian_sources(dims, [112])
+    got = _slabs(env, dims, U, psi, nslab, 0.1245, dagger)[0]
+    want = (wilson.apply_Ddag if dagger else wilson.apply_D)(U, psi[0], dims, 0.1245)
+    assert site_rel_err(got, want) <= 1e-13
+
+
+def test_slabs_multi_rhs(env):
+    dims = (4, 4, 4, 8)
+    U = gauge(dims, 113)
+    psis = synth.gaussian_sources(dims, [114, 115, 116])
+    got = _slabs(env, dims, U, psis, 2, 0.1245, False)
+    for k in range(3):
+        assert site_rel_err(got[k], wilson.apply_D(U, psis[k], dims, 0.1245)) <= 1e-13
+
+
+def test_single_slab_equals_plain_stencil_bitwise(env):
+    """One slab receiving its own faces is the whole (antiperiodic) lattice:
+    bit for bit the plain marching stencil."""
+    torch, dev, wd = env
+    dims = (8, 8, 8, 8)
+    U = gauge(dims, 117)
+    psi = synth.gaussian_spinor(dims, 118)
+    got = _slabs(env, dims, U, psi[None], 1, 0.1245, False)[0]
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    fa, fb = wd.Field(lat, "f64"), wd.Field(lat, "f64")
+    fa.load(torch.from_numpy(psi).to(dev))
+    wd.wd_dslash(lat, 0.1245, 0, fa, fb)
+    o = torch.empty_like(torch.from_numpy(psi)).to(dev)
+    fb.store(o)
+    torch.cuda.synchronize()
+    assert np.array_equal(got, o.cpu().numpy())
+    fa.close()
+    fb.close()
+    lat.close()
+
+
+def test_halo_argument_errors(env):
+    torch, dev, wd = env
+    lat = wd.Lattice((4, 4, 4, 4))
+    f = wd.Field(lat, "f64")
+    g = wd.Field(lat, "f32")
+    n = wd.face_numel(lat)
+    a = torch.zeros(n, dtype=torch.float64, device=dev)
+    b = torch.zeros(n, dtype=torch.float64, device=dev)
+    with pytest.raises(wd.WdError):
+        wd.wd_halo_pack(lat, g, a, b)  # float32 field
+    lat.set_gauge(torch.from_numpy(gauge((4, 4, 4, 4), 1)).to(dev))
+    with pytest.raises(wd.WdError):
+        wd.wd_dslash_halo(lat, 0.1, f, wd.Field(lat, "f64"), a, b, True, True)  # links not set
+    f.close()
+    g.close()
+    lat.close()
