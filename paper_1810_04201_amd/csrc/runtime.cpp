@@ -154,6 +154,8 @@ static void drain_pending_locked() {
     g_pending.clear();
 }
 
+bool timing_enabled() { return g_timing.load(std::memory_order_relaxed) != 0; }
+
 // a stencil launch, bracketed by events on its stream while timing is on
 template <typename F>
 static void timed(const char *name, hipStream_t s, F &&launch) {

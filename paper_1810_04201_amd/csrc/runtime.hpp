@@ -119,6 +119,7 @@ class Solve {
         int slot;
     };
     void enqueue_inner(int iters);
+    int enqueue_chunk();
     void enqueue_reliable();
     void op(bool first, const FieldRef &in, const FieldRef &out, const RedArgs *red, Gate gate,
             bool lo);
@@ -137,6 +138,9 @@ class Solve {
     bool eo_ = false;      // on the even-odd Schur complement
     int chunk_ = 8;
     int rel_every_ = 1;  // inner iterations between gated reliable updates
+    bool use_graph_ = false;
+    hipGraph_t graph_ = nullptr;       // one captured chunk of inner iterations
+    hipGraphExec_t gexec_ = nullptr;
     void *gauge64_ = nullptr, *gauge_lo_ = nullptr;
     void *gh64_[2] = {}, *ghlo_[2] = {};  // even-odd halves
     void *mem_ = nullptr;
@@ -163,5 +167,6 @@ class Solve {
 };
 
 double now_seconds();
+bool timing_enabled();
 
 }  // namespace wd

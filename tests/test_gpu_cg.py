@@ -254,3 +254,37 @@ def test_config2_16x32_true_residual_by_oracle(env):
         bp = wilson.apply_Ddag(U, b, dims, 0.124)
         r = bp - wilson.apply_DdagD(U, x, dims, 0.124)
         assert np.linalg.norm(r) / np.linalg.norm(bp) <= 1.0001e-10, prec
+
+
+@pytest.mark.parametrize("prec,even_odd,nrhs", [("f64", False, 1), ("f16", False, 3),
+                                                ("f32", True, 2)])
+def test_graph_replays_equal_eager(env, monkeypatch, prec, even_odd, nrhs):
+    """On a capturable stream the solver replays one captured chunk of inner
+    iterations as a HIP graph (kernel nodes only), with eager status copies
+    between replays.  Three solves in a row in each mode must agree bit for
+    bit with eager launches (WD_GRAPH=0)."""
+    torch, dev, wd = env
+    dims = (8, 8, 8, 8)
+    U = gauge(dims, 121)
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    B = torch.from_numpy(synth.gaussian_sources(dims, [122 + k for k in range(nrhs)])).to(dev)
+    B = B[0] if nrhs == 1 else B
+    s = torch.cuda.Stream()
+    res = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("WD_GRAPH", mode)
+        xs = []
+        for kappa in (0.12, 0.124, 0.12):
+            x = torch.zeros_like(B)
+            with torch.cuda.stream(s):
+                rc, info = lat.solve(B, x, kappa, tol=1e-10, prec=prec, nrhs=nrhs,
+                                     even_odd=even_odd, stream=s)
+            assert rc == 0
+            torch.cuda.synchronize()
+            xs.append(x.cpu())
+        res[mode] = xs
+    for a, b in zip(res["0"], res["1"]):
+        assert torch.equal(a, b)
+    assert torch.equal(res["1"][0], res["1"][2])
+    lat.close()
