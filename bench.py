@@ -669,6 +669,13 @@ def probe(np, torch, synth, wd):
         fa.close()
         fb.close()
         print(f"probe {prec} done", flush=True)
+    # the even-odd Schur operator: two half-field stencil launches each
+    out = torch.empty_like(psi)
+    for prec in ("f64", "f16"):
+        for _ in range(3):
+            lat.apply_schur(0.1245, psi, out, prec=prec)
+        torch.cuda.synchronize()
+        print(f"probe schur {prec} done", flush=True)
     lat.close()
 
 
@@ -711,6 +718,23 @@ def pmc_summary(args):
             "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk, "traffic_bytes": round(traffic),
             "algorithmic_bytes": alg, "traffic_over_algorithmic": round(traffic / alg, 3),
             "traffic_bytes_per_site": round(traffic / V, 1)}
+    # even-odd half-field stencil (k_hop_half): a launch writes V/2 sites,
+    # reads every link once and the other half's spinors, and (every second
+    # launch of M) a c field
+    for prec, tag in (("f64", "k_hop_half<0"), ("f16", "k_hop_half<2")):
+        fr = [r for r in fetch if tag in r["name"]]
+        wr = [r for r in write if tag in r["name"]]
+        if not fr or not wr:
+            continue
+        fk = statistics.mean(r["FETCH_SIZE"] for r in fr)
+        wk = statistics.mean(r["WRITE_SIZE"] for r in wr)
+        traffic = fk * 1024 * ff + wk * 1024 * wf
+        per_site = 8 * LINK_BYTES[prec] // 4 + 2.5 * SPINOR_BYTES[prec]
+        alg = V // 2 * per_site
+        out["kernels"][f"hop_half_{prec}"] = {
+            "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk, "traffic_bytes": round(traffic),
+            "algorithmic_bytes": alg, "traffic_over_algorithmic": round(traffic / alg, 3),
+            "traffic_bytes_per_output_site": round(traffic / (V // 2), 1)}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
