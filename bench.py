@@ -39,6 +39,13 @@ FLOP_PER_SITE = 1320
 # four links per site (each read once), spinor out once
 BYTES_PER_SITE = {"f64": 192 + 576 + 192, "f32": 96 + 192 + 96, "f16": 52 + 96 + 52}
 LINK_BYTES = {"f64": 576, "f32": 192, "f16": 96}
+# the CG's second stencil with the x/r update fused: links and spinor in as
+# above, p read, x and r read and written (F64, or F32 beside F32/F16 p and
+# q); q itself is never stored
+XR_BYTES_PER_SITE = {"f64": 576 + 192 + 192 + 2 * 192 + 2 * 192,
+                     "f32": 192 + 96 + 96 + 2 * 96 + 2 * 96,
+                     "f16": 96 + 52 + 52 + 2 * 96 + 2 * 96}
+FUSED_XR = os.environ.get("WD_FUSE_XR", "1") != "0"
 SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52}
 HBM_PEAK_GBS = 8000.0
 METRIC = "dslash GFLOP/s & HBM GB/s; CG time-to-1e-10 residual, mixed vs FP64"
@@ -79,19 +86,22 @@ def kernel_source_hash() -> str:
 
 
 def applications(info, prec_inner):
-    """Stencil applications a solve performed, by precision (no-op launches
-    enqueued after convergence do no work and are not counted)."""
+    """Stencil applications a solve performed, by kernel and precision (no-op
+    launches enqueued after convergence do no work and are not counted).  An
+    iteration applies the plain stencil once and, with the fused update, the
+    x/r-updating stencil once ("xr_" keys)."""
     it, up = info["iters"], info["reliable_updates"]
-    f64 = 1 + 2 * max(up - 1, 0) + 1  # D^dag b, reliable updates, final D x
-    inner = 2 * it
-    if prec_inner == "f64":
-        return {"f64": f64 + inner}
-    return {"f64": f64, prec_inner: inner}
+    out = {"f64": 1 + 2 * max(up - 1, 0) + 1}  # D^dag b, reliable updates, final D x
+    out[prec_inner] = out.get(prec_inner, 0) + (it if FUSED_XR else 2 * it)
+    if FUSED_XR:
+        out["xr_" + prec_inner] = it
+    return out
 
 
-def load_traffic(prec):
-    """HBM traffic per launch from the committed counter summary, or None if
-    it is missing or was taken on a different stencil source."""
+def load_traffic(key):
+    """HBM traffic per launch of the stencil kernel `key` ("f64", "xr_f64",
+    ...) from the committed counter summary, or None if it is missing or was
+    taken on a different stencil source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -99,7 +109,7 @@ def load_traffic(prec):
         return None
     if t.get("source_sha256") != kernel_source_hash():
         return None
-    k = t.get("kernels", {}).get(f"dslash_{prec}")
+    k = t.get("kernels", {}).get(f"dslash_{key}")
     return None if k is None else k.get("traffic_bytes")
 
 
@@ -162,7 +172,7 @@ def main():
     wd.wd_timing_enable(True)
     torch.cuda.synchronize()
     t_start = time.time()
-    apps = {"f64": 0, "f32": 0, "f16": 0}
+    apps = {k: 0 for k in ("f64", "f32", "f16", "xr_f64", "xr_f32", "xr_f16")}
     per_step = []
     for k in range(args.steps):
         ts = time.time()
@@ -177,18 +187,50 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.time() - t_start
     wd.wd_timing_enable(False)
-    ms64, _ = wd.wd_timing_read("dslash_f64")
+    ms = {k: wd.wd_timing_read("dslash_" + k)[0] for k in apps}
     msl, cntl = wd.wd_timing_read("dslash_" + args.mixed)
 
     total_apps = sum(apps.values())
     value = total_apps * V * FLOP_PER_SITE / elapsed / 1e9
-    # dominant kernel: the FP64 stencil, average over its real launches
-    avg64_ms = ms64 / apps["f64"]
-    achieved = V * BYTES_PER_SITE["f64"] / (avg64_ms * 1e-3) / 1e9
     t_fp64 = statistics.median(s["fp64"]["seconds"] for s in per_step)
     t_mix = statistics.median(s["mixed"]["seconds"] for s in per_step)
     s0 = per_step[-1]
-    traffic = load_traffic("f64") if dims == (48, 48, 48, 96) else None
+    full = dims == (48, 48, 48, 96)
+
+    def roof(key, what):
+        """HBM roofline of one stencil kernel: average over its working
+        launches in the timed steps."""
+        avg_ms = ms[key] / apps[key]
+        prec = key[-3:]
+        bps = XR_BYTES_PER_SITE[prec] if key.startswith("xr_") else BYTES_PER_SITE[prec]
+        achieved = V * bps / (avg_ms * 1e-3) / 1e9
+        traffic = load_traffic(key) if full else None
+        return {
+            "kernel": what,
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None),
+            "traffic_bytes_per_launch": traffic,
+            "algorithmic_bytes_per_launch": V * bps,
+            "avg_launch_ms": round(avg_ms, 4),
+            "launches": apps[key],
+            "bytes_per_site": bps,
+            "sites_per_launch": V,
+            "copy_GBps": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
+        }
+
+    plain = roof("f64", "dslash_f64 (k_dslash_tm<F64>, time-marching stencil)")
+    # dominant kernel: whichever FP64 stencil kernel took the most time
+    if FUSED_XR and apps["xr_f64"] and ms["xr_f64"] > ms["f64"]:
+        roofline = roof("xr_f64", "dslash_xr_f64 (k_dslash_tm<F64, XR>, time-marching stencil "
+                                  "with the fused CG update x += alpha p, r -= alpha D^dag D p)")
+        roofline["plain_stencil"] = plain
+    else:
+        roofline = plain
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -221,23 +263,7 @@ def main():
             f"mixed_{args.mixed}_true_rel_resid": s0["mixed"]["true_rel_resid"],
             "speedup_mixed_vs_fp64": round(t_fp64 / t_mix, 3),
         },
-        "roofline": {
-            "kernel": "dslash_f64 (k_dslash_tm<F64>, time-marching stencil)",
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (round(traffic / (avg64_ms * 1e-3) / 1e9, 1) if traffic else None),
-            "traffic_bytes_per_launch": traffic,
-            "algorithmic_bytes_per_launch": V * BYTES_PER_SITE["f64"],
-            "avg_launch_ms": round(avg64_ms, 4),
-            "launches": apps["f64"],
-            "bytes_per_site": BYTES_PER_SITE["f64"],
-            "sites_per_launch": V,
-            "copy_GBps": round(copy_gbs, 1),
-            "frac_of_copy": round(achieved / copy_gbs, 4),
-        },
+        "roofline": roofline,
     }
     if cntl:
         ml = msl / apps[args.mixed]
@@ -246,6 +272,12 @@ def main():
             "achieved_GBps": round(V * BYTES_PER_SITE[args.mixed] / (ml * 1e-3) / 1e9, 1),
             "GFLOPs": round(V * FLOP_PER_SITE / (ml * 1e-3) / 1e9, 1),
         }
+        if apps["xr_" + args.mixed]:
+            mx = ms["xr_" + args.mixed] / apps["xr_" + args.mixed]
+            out["roofline_" + args.mixed]["xr"] = {
+                "avg_launch_ms": round(mx, 4),
+                "achieved_GBps": round(V * XR_BYTES_PER_SITE[args.mixed] / (mx * 1e-3) / 1e9, 1),
+                "bytes_per_site": XR_BYTES_PER_SITE[args.mixed]}
     if not args.no_extras:
         ex = {}
         ex.update(stencil_alone(wd, torch, lat, bd, V, kappa, stream))
@@ -676,6 +708,13 @@ def probe(np, torch, synth, wd):
             lat.apply_schur(0.1245, psi, out, prec=prec)
         torch.cuda.synchronize()
         print(f"probe schur {prec} done", flush=True)
+    # CG iterations (the stencil with the fused x/r update), FP64 and mixed
+    x = torch.zeros_like(psi)
+    for prec in ("f64", "f16"):
+        x.zero_()
+        lat.solve(psi, x, 0.1245, tol=1e-10, prec=prec, max_iter=4)
+        torch.cuda.synchronize()
+        print(f"probe cg {prec} done", flush=True)
     lat.close()
 
 
@@ -704,17 +743,28 @@ def pmc_summary(args):
            "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
                                 "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
            "kernels": {}}
-    for prec, tag in (("f64", "k_dslash_tm<0"), ("f32", "k_dslash_tm<1"), ("f16", "k_dslash_tm<2")):
+    grp = {"f64": 1, "f32": 2, "f16": 2}
+    kinds = []
+    for i, prec in enumerate(("f64", "f32", "f16")):
+        # the plain stencil (D, no reduction) and the CG's x/r-updating D^dag
+        kinds.append((prec, f"k_dslash_tm<{i}, false, false, {grp[prec]}, false, false>",
+                      BYTES_PER_SITE[prec]))
+        kinds.append(("xr_" + prec, f"k_dslash_tm<{i}, true, true, {grp[prec]}, false, true>",
+                      XR_BYTES_PER_SITE[prec]))
+    for key, tag, bps in kinds:
         fr = [r for r in fetch if tag in r["name"]]
         wr = [r for r in write if tag in r["name"]]
         if not fr or not wr:
             continue
-        big = max(r["grid"] for r in fr)
-        fk = statistics.median(r["FETCH_SIZE"] for r in fr if r["grid"] == big)
-        wk = statistics.median(r["WRITE_SIZE"] for r in wr if r["grid"] == big)
+        # launches that did work (a solve's launches after it stopped return
+        # at once)
+        fm = max(r["FETCH_SIZE"] for r in fr)
+        wm = max(r["WRITE_SIZE"] for r in wr)
+        fk = statistics.median(r["FETCH_SIZE"] for r in fr if r["FETCH_SIZE"] > 0.5 * fm)
+        wk = statistics.median(r["WRITE_SIZE"] for r in wr if r["WRITE_SIZE"] > 0.5 * wm)
         traffic = fk * 1024 * ff + wk * 1024 * wf
-        alg = V * BYTES_PER_SITE[prec]
-        out["kernels"][f"dslash_{prec}"] = {
+        alg = V * bps
+        out["kernels"][f"dslash_{key}"] = {
             "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk, "traffic_bytes": round(traffic),
             "algorithmic_bytes": alg, "traffic_over_algorithmic": round(traffic / alg, 3),
             "traffic_bytes_per_site": round(traffic / V, 1)}

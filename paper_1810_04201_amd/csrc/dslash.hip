@@ -303,6 +303,33 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
     if (RED) reduce_block(nrm, red.partials, (size_t)sb * nrhs + rhs);
 }
 
+// x += alpha p, r -= alpha q at site i of one rhs (x, r in F64, or F32 beside
+// F32/F16 p), in the compute type of the stencil; returns |r|^2 in float64.
+// The same arithmetic as the stand-alone update of the solver, on the
+// stencil's unrounded q.
+template <int PREC>
+__device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
+                                          typename Spinor<PREC>::R alpha,
+                                          const cx<typename Spinor<PREC>::R> q[12]) {
+    constexpr int PX = PREC == WD_F64 ? WD_F64 : WD_F32;
+    using R = typename Spinor<PREC>::R;
+    const FieldRef xf = rhs_view(a.x, rhs), rf = rhs_view(a.r, rhs);
+    cx<R> v[12], w[12];
+    Spinor<PREC>::load(rhs_view(a.p, rhs), i, w);
+    Spinor<PX>::load(xf, i, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = {v[k].re + alpha * w[k].re, v[k].im + alpha * w[k].im};
+    Spinor<PX>::template store<WD_NT_OUT>(xf, i, v);
+    Spinor<PX>::load(rf, i, v);
+    double nrm = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        v[k] = {v[k].re - alpha * q[k].re, v[k].im - alpha * q[k].im};
+        nrm += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
+    }
+    Spinor<PX>::template store<WD_NT_OUT>(rf, i, v);
+    return nrm;
+}
 
 // Time-marching stencil.  One workgroup per brick column, chunk of time
 // slices, part of the brick slice (all of it, or a contiguous half or
@@ -328,11 +355,14 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
 // ends read staged faces (see Halo) in place of the wrapped slices: only the
 // sources of the prologue's spinor and link, of the last step's slice copy,
 // and the boundary sign change.
-template <int PREC, bool DAG, bool RED, int GROUP, bool HALO = false>
+// XR: the CG update that consumes q = A p is done where q is formed, so q is
+// never stored: x += alpha p, r -= alpha q, and the reduction is |r|^2 (see
+// XrArgs).  out is unused.
+template <int PREC, bool DAG, bool RED, int GROUP, bool HALO = false, bool XR = false>
 __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *__restrict__ gauge,
                                                    FieldRef in, FieldRef out, double kappa_d,
                                                    RedArgs red, Gate gate, int tchunk,
-                                                   int ncols, Halo halo) {
+                                                   int ncols, Halo halo, XrArgs xr) {
     using R = typename Spinor<PREC>::R;
     extern __shared__ __align__(16) char lds[];
     __shared__ double wsum[kTmMaxBlock / 64];
@@ -455,9 +485,13 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             c[k] = c[k] - scale(kappa, acc[k]);
-            if (RED) nrm += (double)c[k].re * (double)c[k].re + (double)c[k].im * (double)c[k].im;
+            if (RED && !XR)
+                nrm += (double)c[k].re * (double)c[k].re + (double)c[k].im * (double)c[k].im;
         }
-        Spinor<PREC>::template store<WD_NT_OUT>(fout, i, c);
+        if (XR)
+            nrm = xr_site<PREC>(xr, rhs, i, (R)gate.st[rhs].alpha, c);
+        else
+            Spinor<PREC>::template store<WD_NT_OUT>(fout, i, c);
         if (RED) {
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
@@ -524,7 +558,7 @@ static void launch_tm_k(dim3 grid, dim3 bs, size_t lds, hipStream_t s, const Geo
     auto k = k_dslash_tm<PREC, DAG, RED, G>;
     allow_lds(k, lds);
     hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols,
-                       Halo{nullptr, nullptr, nullptr, 0, 0});
+                       Halo{nullptr, nullptr, nullptr, 0, 0}, XrArgs{});
 }
 
 template <int PREC>
@@ -589,6 +623,56 @@ void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, F
         case WD_F64: launch_prec<WD_F64>(g, gauge, kappa, dagger, in, out, red, gate, s); break;
         case WD_F32: launch_prec<WD_F32>(g, gauge, kappa, dagger, in, out, red, gate, s); break;
         default: launch_prec<WD_F16>(g, gauge, kappa, dagger, in, out, red, gate, s); break;
+    }
+}
+
+template <int PREC>
+static bool xr_ok(const Geom &g, int nrhs, int partials_cap) {
+    return tm_eligible(g) && tm_fits<PREC>(g) && !g_force_site_kernel &&
+           (int64_t)(g.V / tm_wvol(g, PREC)) * nrhs <= partials_cap;
+}
+
+bool dslash_xr_supported(const Geom &g, int prec, int nrhs, int partials_cap) {
+    switch (prec) {
+        case WD_F64: return xr_ok<WD_F64>(g, nrhs, partials_cap);
+        case WD_F32: return xr_ok<WD_F32>(g, nrhs, partials_cap);
+        default: return xr_ok<WD_F16>(g, nrhs, partials_cap);
+    }
+}
+
+template <int PREC>
+static bool xr_prec(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
+                    const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s) {
+    if (!xr_ok<PREC>(g, in.nrhs, red.partials_cap)) return false;
+    const int wvol = tm_wvol(g, PREC);
+    const int nsub = g.bvol / wvol;
+    const int tch = tm_chunk(g, in.nrhs * nsub);
+    const int ncols = g.V / (g.L[3] * g.bvol);
+    const dim3 grid(tm_blocks(g, tch) * nsub * in.nrhs), bs(wvol);
+    const size_t lds = 2 * slice_bytes<PREC>(wvol);
+    constexpr int G = HopGroup<PREC>::value;
+    const Halo nh{nullptr, nullptr, nullptr, 0, 0};
+    if (dagger) {
+        auto k = k_dslash_tm<PREC, true, true, G, false, true>;
+        allow_lds(k, lds);
+        hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, FieldRef{}, kappa, red, gate, tch,
+                           ncols, nh, xr);
+    } else {
+        auto k = k_dslash_tm<PREC, false, true, G, false, true>;
+        allow_lds(k, lds);
+        hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, FieldRef{}, kappa, red, gate, tch,
+                           ncols, nh, xr);
+    }
+    launch_finalize(red, g.V / wvol, gate.batch ? gate.mode : -1, s);
+    return true;
+}
+
+bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
+                      const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s) {
+    switch (in.prec) {
+        case WD_F64: return xr_prec<WD_F64>(g, gauge, kappa, dagger, in, xr, red, gate, s);
+        case WD_F32: return xr_prec<WD_F32>(g, gauge, kappa, dagger, in, xr, red, gate, s);
+        default: return xr_prec<WD_F16>(g, gauge, kappa, dagger, in, xr, red, gate, s);
     }
 }
 
@@ -819,12 +903,12 @@ void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagg
         auto k = k_dslash_tm<WD_F64, true, false, G, true>;
         allow_lds(k, lds);
         hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, RedArgs{}, none, tch,
-                           ncols, halo);
+                           ncols, halo, XrArgs{});
     } else {
         auto k = k_dslash_tm<WD_F64, false, false, G, true>;
         allow_lds(k, lds);
         hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, RedArgs{}, none, tch,
-                           ncols, halo);
+                           ncols, halo, XrArgs{});
     }
 }
 

@@ -186,6 +186,17 @@ void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const 
           [&] { launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s); });
 }
 
+bool dslash_xr(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
+               const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s) {
+    if (!dslash_xr_supported(lat->g, in.prec, in.nrhs, red.partials_cap)) return false;
+    kappa = -lat->hop_sign * kappa;
+    static const char *names[3] = {"dslash_xr_f64", "dslash_xr_f32", "dslash_xr_f16"};
+    bool ok = false;
+    timed(names[in.prec], s,
+          [&] { ok = launch_dslash_xr(lat->g, gauge, kappa, dagger, in, xr, red, gate, s); });
+    return ok;
+}
+
 void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
               const FieldRef &in, const FieldRef &c, const FieldRef &out, const RedArgs *red,
               Gate gate, hipStream_t s) {

@@ -74,6 +74,11 @@ void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs
 void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
             const FieldRef &out, const RedArgs *red, Gate gate, hipStream_t s);
 
+// stencil launch fused with the CG update that consumes its output (see
+// launch_dslash_xr), with optional event timing; false if not supported
+bool dslash_xr(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
+               const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s);
+
 FieldRef carve(char *&cursor, int prec, int nrhs, int V);
 
 // ------------------------------------------------------------------ solve
@@ -136,6 +141,7 @@ class Solve {
     int prec_;
     int d1_ = 0, d2_ = 1;  // daggers of the two operators of the normal equations
     bool eo_ = false;      // on the even-odd Schur complement
+    bool fuse_xr_ = false;  // the second operator application does the x/r update
     int chunk_ = 8;
     int rel_every_ = 1;  // inner iterations between gated reliable updates
     bool use_graph_ = false;

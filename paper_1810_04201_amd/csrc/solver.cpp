@@ -207,6 +207,12 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     // are being timed; WD_GRAPH=0 turns it off.
     const char *ge = getenv("WD_GRAPH");
     use_graph_ = s_ != nullptr && !timing_enabled() && !(ge && atoi(ge) == 0);
+    // A^dag (A p) formed where x and r are updated (q never stored): 2 of
+    // the 9 field transfers of an iteration's vector updates saved.  The
+    // marching stencil on the full lattice only; WD_FUSE_XR=0 turns it off.
+    const char *fx = getenv("WD_FUSE_XR");
+    fuse_xr_ = !eo_ && !(fx && atoi(fx) == 0) &&
+               dslash_xr_supported(lat_->g, prec_, nrhs, partials_cap_);
     return WD_OK;
 }
 
@@ -288,8 +294,11 @@ void Solve::enqueue_inner(int iters) {
     RedArgs rr = red(RED_RR);
     for (int i = 0; i < iters; ++i) {
         op(true, pl_, tl_, &ra, g, true);
-        op(false, tl_, apl_, nullptr, g, true);
-        launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
+        if (!fuse_xr_ || !dslash_xr(lat_, gauge_lo_, p_.kappa, d2_, tl_, XrArgs{xl_, rl_, pl_},
+                                    rr, g, s_)) {
+            op(false, tl_, apl_, nullptr, g, true);
+            launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
+        }
         launch_update_p(pl_, rl_, g, s_);
         if ((i + 1) % rel_every_ == 0 || i + 1 == iters) enqueue_reliable();
     }

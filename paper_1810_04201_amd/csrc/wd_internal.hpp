@@ -246,6 +246,12 @@ struct Gate {
 //   links:       U_t(x, -1), the links entering from the previous slab
 //                (float64 gauge tiles of V / Lt sites, mu = 3 planes)
 //   first, last: this slab holds global t = 0 / t = T - 1 (antiperiodic sign)
+// The CG update x += alpha p, r -= alpha q done by the stencil that forms
+// q = A p, so q is never stored (alpha from the rhs's state)
+struct XrArgs {
+    FieldRef x, r, p;
+};
+
 struct Halo {
     const void *prev;
     const void *next;
@@ -470,6 +476,13 @@ void launch_accum_zero(FieldRef x64, FieldRef xlo, Gate gate, hipStream_t s);
 // reduction of |out|^2 with red->mode
 void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                    FieldRef out, const RedArgs *red, Gate gate, hipStream_t s);
+// q = D in (or D^dag in) consumed where it is formed: x += alpha p,
+// r -= alpha q, |r|^2 reduced with red.mode (RED_RR) and finalised; q is not
+// stored.  Only the marching stencil does this: returns false (nothing
+// launched) where it does not run
+bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
+                      const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s);
+bool dslash_xr_supported(const Geom &g, int prec, int nrhs, int partials_cap);
 
 // x += alpha p ; r -= alpha Ap ; reduce |r|^2 (red.mode = RED_RR); active rhs
 void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const RedArgs &red,

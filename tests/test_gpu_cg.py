@@ -288,3 +288,46 @@ def test_graph_replays_equal_eager(env, monkeypatch, prec, even_odd, nrhs):
         assert torch.equal(a, b)
     assert torch.equal(res["1"][0], res["1"][2])
     lat.close()
+
+
+@pytest.mark.parametrize("prec,nrhs", [("f64", 1), ("f32", 2), ("f16", 3)])
+def test_fused_update_equals_separate_update(env, monkeypatch, prec, nrhs):
+    """The second stencil of an iteration updates x and r where it forms
+    q = A^dag A p (q is never stored); WD_FUSE_XR=0 stores q and updates in a
+    separate kernel.  In FP64 and FP32 the x/r arithmetic is the same and
+    only the summation order of |r|^2 differs; with FP16 the fused update
+    uses q before its rounding to FP16.  Both paths reach the oracle's
+    solution, with the same iteration counts (+-1 in FP64)."""
+    torch, dev, wd = env
+    dims = (8, 8, 8, 8)
+    kappa = 0.124
+    U = gauge(dims, 131)
+    B = synth.gaussian_sources(dims, [132 + k for k in range(nrhs)])
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    Bd = torch.from_numpy(B).to(dev)
+    Bd = Bd[0] if nrhs == 1 else Bd
+    res = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("WD_FUSE_XR", mode)
+        wd.wd_timing_reset()
+        wd.wd_timing_enable(True)
+        x = torch.zeros_like(Bd)
+        rc, info = lat.solve(Bd, x, kappa, tol=1e-10, prec=prec, nrhs=nrhs)
+        torch.cuda.synchronize()
+        wd.wd_timing_enable(False)
+        assert rc == 0, info
+        _, n_xr = wd.wd_timing_read("dslash_xr_" + prec)
+        assert (n_xr > 0) == (mode == "1")
+        res[mode] = (x.cpu().numpy().reshape(B.shape), info)
+    lat.close()
+    xo, it, oinfo = _oracle(dims, U, B[0], kappa, 1e-12)
+    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+    (xf, inf_f), (xu, inf_u) = res["1"], res["0"]
+    for k in range(nrhs):
+        assert inf_f[k]["true_rel_resid"] <= 1e-10 and inf_u[k]["true_rel_resid"] <= 1e-10
+        if prec == "f64":
+            assert abs(inf_f[k]["iters"] - inf_u[k]["iters"]) <= 1
+            assert rel(xf[k], xu[k]) <= 1e-9
+    assert rel(xf[0], xo) <= max(1e-9, 2e-10 * cond)
+    assert rel(xu[0], xo) <= max(1e-9, 2e-10 * cond)
