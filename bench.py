@@ -46,6 +46,17 @@ XR_BYTES_PER_SITE = {"f64": 576 + 192 + 192 + 2 * 192 + 2 * 192,
                      "f32": 192 + 96 + 96 + 2 * 96 + 2 * 96,
                      "f16": 96 + 52 + 52 + 2 * 96 + 2 * 96}
 FUSED_XR = os.environ.get("WD_FUSE_XR", "1") != "0"
+# the slab stencil reads float64 links as 18 reals
+HALO_BYTES_PER_SITE = 192 + 576 + 192
+
+
+def f64_bytes(lat):
+    """Per-site algorithmic bytes of the float64 marching stencil and of its
+    x/r-updating form on this lattice: its links are read as 12 reals (384
+    bytes per site) when wd_set_gauge found them special unitary, else 18
+    (576)."""
+    link = 384 if lat.links_info()[0] == 12 else 576
+    return 192 + link + 192, link + 192 + 192 + 2 * 192 + 2 * 192
 SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52}
 HBM_PEAK_GBS = 8000.0
 METRIC = "dslash GFLOP/s & HBM GB/s; CG time-to-1e-10 residual, mixed vs FP64"
@@ -188,6 +199,8 @@ def main():
     elapsed = time.time() - t_start
     wd.wd_timing_enable(False)
     ms = {k: wd.wd_timing_read("dslash_" + k)[0] for k in apps}
+    BYTES_PER_SITE["f64"], XR_BYTES_PER_SITE["f64"] = f64_bytes(lat)
+    f64_link_reals = lat.links_info()[0]
     msl, cntl = wd.wd_timing_read("dslash_" + args.mixed)
 
     total_apps = sum(apps.values())
@@ -223,11 +236,13 @@ def main():
             "frac_of_copy": round(achieved / copy_gbs, 4),
         }
 
-    plain = roof("f64", "dslash_f64 (k_dslash_tm<F64>, time-marching stencil)")
+    plain = roof("f64", f"dslash_f64 (k_dslash_tm<F64>, time-marching stencil, "
+                        f"F64-{f64_link_reals} links)")
     # dominant kernel: whichever FP64 stencil kernel took the most time
     if FUSED_XR and apps["xr_f64"] and ms["xr_f64"] > ms["f64"]:
-        roofline = roof("xr_f64", "dslash_xr_f64 (k_dslash_tm<F64, XR>, time-marching stencil "
-                                  "with the fused CG update x += alpha p, r -= alpha D^dag D p)")
+        roofline = roof("xr_f64", f"dslash_xr_f64 (k_dslash_tm<F64, XR>, time-marching stencil "
+                                  f"with the fused CG update x += alpha p, r -= alpha D^dag D p, "
+                                  f"F64-{f64_link_reals} links)")
         roofline["plain_stencil"] = plain
     else:
         roofline = plain
@@ -363,7 +378,7 @@ def slab_share(np, torch, synth, wd):
     res = {"lattice": "48x48x48x12 (one of 8 t-slabs of 48x48x48x96)",
            "dslash_plain_ms": round(plain, 4), "halo_pack_ms": round(pack, 4),
            "dslash_halo_ms": round(halo, 4),
-           "dslash_halo_GBps_algorithmic": round(V * BYTES_PER_SITE["f64"] / halo / 1e6, 1),
+           "dslash_halo_GBps_algorithmic": round(V * HALO_BYTES_PER_SITE / halo / 1e6, 1),
            "face_bytes_per_direction": face_bytes,
            "face_over_xgmi_link_us_estimate": round(face_bytes / 153e9 * 1e6, 1)}
     fa.close()
@@ -419,7 +434,8 @@ def small_configs(np, torch, synth, wd):
                 ms = e0.elapsed_time(e1) / 20
                 r[f"dslash_{prec}_ms"] = round(ms, 4)
                 r[f"dslash_{prec}_GFLOPs"] = round(V * FLOP_PER_SITE / ms / 1e6, 1)
-                r[f"dslash_{prec}_GBps_l2_miss"] = round(V * BYTES_PER_SITE[prec] / ms / 1e6, 1)
+                bps = f64_bytes(lat)[0] if prec == "f64" else BYTES_PER_SITE[prec]
+                r[f"dslash_{prec}_GBps_l2_miss"] = round(V * bps / ms / 1e6, 1)
                 fa.close()
                 fb.close()
         lat.close()
@@ -447,9 +463,11 @@ def stencil_alone(wd, torch, lat, bd, V, kappa, stream):
             e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / n
+        bps = f64_bytes(lat)[0] if prec == "f64" else BYTES_PER_SITE[prec]
         res[f"dslash_{prec}"] = {"ms": round(ms, 4),
                                  "GFLOPs": round(V * FLOP_PER_SITE / ms / 1e6, 1),
-                                 "GBps_algorithmic": round(V * BYTES_PER_SITE[prec] / ms / 1e6, 1)}
+                                 "GBps_algorithmic": round(V * bps / ms / 1e6, 1),
+                                 "bytes_per_site": bps}
         fa.close()
         fb.close()
     log(f"stencil alone: {res}")
@@ -746,11 +764,17 @@ def pmc_summary(args):
     grp = {"f64": 1, "f32": 2, "f16": 2}
     kinds = []
     for i, prec in enumerate(("f64", "f32", "f16")):
-        # the plain stencil (D, no reduction) and the CG's x/r-updating D^dag
-        kinds.append((prec, f"k_dslash_tm<{i}, false, false, {grp[prec]}, false, false>",
-                      BYTES_PER_SITE[prec]))
-        kinds.append(("xr_" + prec, f"k_dslash_tm<{i}, true, true, {grp[prec]}, false, true>",
-                      XR_BYTES_PER_SITE[prec]))
+        # the plain stencil (D, no reduction) and the CG's x/r-updating D^dag;
+        # float64 with its 12-real (form 3) or 18-real links
+        forms = ((3, 384), (0, 576)) if prec == "f64" else ((i, None),)
+        for lf, link in forms:
+            b, bx = BYTES_PER_SITE[prec], XR_BYTES_PER_SITE[prec]
+            if link is not None:
+                b, bx = b - 576 + link, bx - 576 + link
+            kinds.append((prec, f"k_dslash_tm<{i}, false, false, {grp[prec]}, false, false, {lf}>",
+                          b))
+            kinds.append(("xr_" + prec,
+                          f"k_dslash_tm<{i}, true, true, {grp[prec]}, false, true, {lf}>", bx))
     for key, tag, bps in kinds:
         fr = [r for r in fetch if tag in r["name"]]
         wr = [r for r in write if tag in r["name"]]
@@ -764,9 +788,12 @@ def pmc_summary(args):
         wk = statistics.median(r["WRITE_SIZE"] for r in wr if r["WRITE_SIZE"] > 0.5 * wm)
         traffic = fk * 1024 * ff + wk * 1024 * wf
         alg = V * bps
+        if f"dslash_{key}" in out["kernels"]:
+            continue  # a probe runs one link form per precision
         out["kernels"][f"dslash_{key}"] = {
             "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk, "traffic_bytes": round(traffic),
-            "algorithmic_bytes": alg, "traffic_over_algorithmic": round(traffic / alg, 3),
+            "algorithmic_bytes": alg, "algorithmic_bytes_per_site": bps,
+            "traffic_over_algorithmic": round(traffic / alg, 3),
             "traffic_bytes_per_site": round(traffic / V, 1)}
     # even-odd half-field stencil (k_hop_half): a launch writes V/2 sites,
     # reads every link once and the other half's spinors, and (every second

@@ -108,9 +108,20 @@ int wd_lattice_volume(const wd_lattice *lat, int64_t *volume);
 /* Gauge ingest (Sec. 2.3: links are loaded once and stay resident).
  * U: canonical float64 device array (72 doubles per site).  Packs the
  * float64 18-real form now (the low-precision 12-real forms are derived
- * from it on first use).  The library keeps its own copy; U may be freed
- * after the stream reaches this point.  Synchronises `stream`. */
+ * from it on first use).  It also measures how far each link is from
+ * special unitary (the largest |row 2 - conj(row 0 x row 1)|, Sec. 6.1's
+ * compressed form); if no link is further than 1e-14, the float64 links are
+ * kept as 12 reals too, and every float64 stencil on the full lattice reads
+ * that form (384 instead of 576 link bytes per site; the rebuilt row agrees
+ * to rounding).  Environment WD_LINKS64_12=0 skips the check and the form.
+ * The library keeps its own copy; U may be freed after the stream reaches
+ * this point.  Synchronises `stream`. */
 int wd_set_gauge(wd_lattice *lat, const double *U, void *stream);
+
+/* Float64 link storage chosen by the last wd_set_gauge: *f64_link_reals =
+ * 12 or 18 and *su3_deviation = the largest row-2 deviation it measured
+ * (-1 if it did not check).  Either pointer may be NULL. */
+int wd_lattice_links_info(const wd_lattice *lat, int *f64_link_reals, double *su3_deviation);
 
 /* Bytes of device memory the lattice's packed gauge forms use now. */
 int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes);

@@ -86,6 +86,7 @@ _SIGS = {
     "wd_lattice_volume": [_vp, ctypes.POINTER(ctypes.c_int64)],
     "wd_set_gauge": [_vp, _vp, _vp],
     "wd_lattice_gauge_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
+    "wd_lattice_links_info": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
     "wd_apply_D": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp],
     "wd_apply_Ddag": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp],
     "wd_apply": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
@@ -297,6 +298,14 @@ class Lattice:
 
     def set_gauge(self, U, stream=None):
         wd_set_gauge(self.handle, U, self.volume, stream)
+
+    def links_info(self):
+        """(float64 link reals 12 or 18, largest row-2 deviation from special
+        unitary measured by set_gauge, -1 if unchecked)."""
+        n = ctypes.c_int()
+        d = ctypes.c_double()
+        _check(lib.wd_lattice_links_info(self.handle, ctypes.byref(n), ctypes.byref(d)))
+        return n.value, d.value
 
     def gauge_bytes(self) -> int:
         b = ctypes.c_size_t()

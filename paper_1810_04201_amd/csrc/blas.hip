@@ -96,11 +96,53 @@ void launch_pack_gauge_f64(const double *canon, void *g64, const Geom &geo, hipS
                        (const double2 *)canon, g64, geo);
 }
 
-void launch_gauge_lo(const void *g64, void *glo, int prec, int V, hipStream_t s) {
-    if (prec == WD_F32)
-        hipLaunchKernelGGL(k_gauge_lo<WD_F32>, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s, g64, glo, V);
+void launch_gauge_lo(const void *g64, void *glo, int form, int V, hipStream_t s) {
+    const dim3 gr(blocks_for(V, kBS)), bs(kBS);
+    if (form == WD_F32)
+        hipLaunchKernelGGL(k_gauge_lo<WD_F32>, gr, bs, 0, s, g64, glo, V);
+    else if (form == WD_F16)
+        hipLaunchKernelGGL(k_gauge_lo<WD_F16>, gr, bs, 0, s, g64, glo, V);
     else
-        hipLaunchKernelGGL(k_gauge_lo<WD_F16>, dim3(blocks_for(V, kBS)), dim3(kBS), 0, s, g64, glo, V);
+        hipLaunchKernelGGL(k_gauge_lo<kLinkF64R12>, gr, bs, 0, s, g64, glo, V);
+}
+
+// Largest deviation of a stored row 2 from conj(row 0 x row 1): per block in
+// LDS, then one atomic maximum on the bit pattern (non-negative doubles
+// order like their patterns)
+__global__ void __launch_bounds__(256) k_su3_check(const void *__restrict__ g, int V,
+                                                   unsigned long long *maxbits) {
+    __shared__ double wmax[256 / 64];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (i < V) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            cx<double> u[9], r[9];
+            Link<WD_F64>::load(g, mu, i, u);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) r[k] = u[k];
+            reconstruct_row2(r);
+#pragma unroll
+            for (int j = 6; j < 9; ++j) {
+                const double dr = u[j].re - r[j].re, di = u[j].im - r[j].im;
+                const double d = sqrt(dr * dr + di * di);
+                if (!(d <= e)) e = d == d ? d : INFINITY;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) e = fmax(e, __shfl_xor(e, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wmax[w]);
+        atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+void launch_su3_check(const void *g64, int V, unsigned long long *maxbits, hipStream_t s) {
+    hipLaunchKernelGGL(k_su3_check, dim3(blocks_for(V, 256)), dim3(256), 0, s, g64, V, maxbits);
 }
 
 // even-odd: links of the parity-p sites in the half layout and format PREC

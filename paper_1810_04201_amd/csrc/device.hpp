@@ -200,6 +200,26 @@ struct Link<WD_F64> {
 };
 
 template <>
+struct Link<kLinkF64R12> {
+    using R = double;
+    static constexpr size_t kTileBytes = 24 * 1024;
+    template <bool NT = false>
+    static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const d2_t d = ldv<NT>((const d2_t *)tile_elem(g, kTileBytes, s, mu * 6 + k));
+            u[k] = {d.x, d.y};
+        }
+        reconstruct_row2(u);
+    }
+    static __device__ __forceinline__ void store(void *g, int mu, int s, const cx<double> u[9]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            *(double2 *)tile_elem(g, kTileBytes, s, mu * 6 + k) = make_double2(u[k].re, u[k].im);
+    }
+};
+
+template <>
 struct Link<WD_F32> {
     using R = float;
     static constexpr size_t kTileBytes = 12 * 1024;

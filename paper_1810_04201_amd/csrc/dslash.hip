@@ -216,7 +216,7 @@ __device__ __forceinline__ void slice_copy(const FieldRef &f, int tile0, char *i
 // one spatial hop of the marching stencil: the neighbour comes from the LDS
 // image when it lies in this workgroup's part of the slice (wvol sites from
 // sbase), else (a brick face, or another part of the slice) from memory
-template <int MU, int S, bool BWD, int PREC>
+template <int MU, int S, bool BWD, int PREC, int LF = PREC>
 __device__ __forceinline__ void hop_s(const void *gauge, const FieldRef &in, const FieldRef &cur,
                                       int sbase, int wvol, int nbr, int link_site,
                                       cx<typename Spinor<PREC>::R> acc[12]) {
@@ -230,7 +230,7 @@ __device__ __forceinline__ void hop_s(const void *gauge, const FieldRef &in, con
     cx<R> h0[3], h1[3];
     project<MU, S>(p, h0, h1);
     cx<R> u[9];
-    Link<PREC>::template load<WD_NT_LINK && !BWD>(gauge, MU, link_site, u);
+    Link<LF>::template load<WD_NT_LINK && !BWD>(gauge, MU, link_site, u);
     cx<R> w0[3], w1[3];
     su3_mul<BWD>(u, h0, w0);
     su3_mul<BWD>(u, h1, w1);
@@ -358,7 +358,9 @@ __device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
 // XR: the CG update that consumes q = A p is done where q is formed, so q is
 // never stored: x += alpha p, r -= alpha q, and the reduction is |r|^2 (see
 // XrArgs).  out is unused.
-template <int PREC, bool DAG, bool RED, int GROUP, bool HALO = false, bool XR = false>
+// LF: the link form (PREC's own, or F64-12 for float64; not with HALO).
+template <int PREC, bool DAG, bool RED, int GROUP, bool HALO = false, bool XR = false,
+          int LF = PREC>
 __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *__restrict__ gauge,
                                                    FieldRef in, FieldRef out, double kappa_d,
                                                    RedArgs red, Gate gate, int tchunk,
@@ -423,8 +425,11 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
             h1[c] = scale(sg, h1[c]);
         }
         cx<R> u[9];
-        Link<PREC>::load(prev_from_halo ? halo.links : gauge, 3, prev_from_halo ? fbase + l : ip,
-                         u);
+        if constexpr (HALO)
+            Link<PREC>::load(prev_from_halo ? halo.links : gauge, 3,
+                             prev_from_halo ? fbase + l : ip, u);
+        else
+            Link<LF>::load(gauge, 3, ip, u);
         su3_mul<true>(u, h0, cw0);
         su3_mul<true>(u, h1, cw1);
     }
@@ -447,21 +452,21 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
         for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
 #define WD_HOP_FENCE(k) \
     if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
-        hop_s<0, SF, false, PREC>(gauge, fin, cur, sbase, wvol, nb.xp, i, acc);
+        hop_s<0, SF, false, PREC, LF>(gauge, fin, cur, sbase, wvol, nb.xp, i, acc);
         WD_HOP_FENCE(1);
-        hop_s<0, SB, true, PREC>(gauge, fin, cur, sbase, wvol, nb.xm, nb.xm, acc);
+        hop_s<0, SB, true, PREC, LF>(gauge, fin, cur, sbase, wvol, nb.xm, nb.xm, acc);
         WD_HOP_FENCE(2);
-        hop_s<1, SF, false, PREC>(gauge, fin, cur, sbase, wvol, nb.yp, i, acc);
+        hop_s<1, SF, false, PREC, LF>(gauge, fin, cur, sbase, wvol, nb.yp, i, acc);
         WD_HOP_FENCE(3);
-        hop_s<1, SB, true, PREC>(gauge, fin, cur, sbase, wvol, nb.ym, nb.ym, acc);
+        hop_s<1, SB, true, PREC, LF>(gauge, fin, cur, sbase, wvol, nb.ym, nb.ym, acc);
         WD_HOP_FENCE(4);
-        hop_s<2, SF, false, PREC>(gauge, fin, cur, sbase, wvol, nb.zp, i, acc);
+        hop_s<2, SF, false, PREC, LF>(gauge, fin, cur, sbase, wvol, nb.zp, i, acc);
         WD_HOP_FENCE(5);
-        hop_s<2, SB, true, PREC>(gauge, fin, cur, sbase, wvol, nb.zm, nb.zm, acc);
+        hop_s<2, SB, true, PREC, LF>(gauge, fin, cur, sbase, wvol, nb.zm, nb.zm, acc);
         WD_HOP_FENCE(6);
 #undef WD_HOP_FENCE
         cx<R> ut[9];
-        Link<PREC>::template load<WD_NT_LINK || WD_NT_LINK_T>(gauge, 3, i, ut);
+        Link<LF>::template load<WD_NT_LINK || WD_NT_LINK_T>(gauge, 3, i, ut);
         // the next slice has landed in LDS (every wave's copy)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -550,18 +555,18 @@ static bool tm_fits(const Geom &g) {
     return 2 * slice_bytes<PREC>(tm_wvol(g, PREC)) + 64 <= cap;
 }
 
-template <int PREC, bool DAG, bool RED>
+template <int PREC, bool DAG, bool RED, int LF = PREC>
 static void launch_tm_k(dim3 grid, dim3 bs, size_t lds, hipStream_t s, const Geom &g,
                         const void *gauge, FieldRef in, FieldRef out, double kappa,
                         const RedArgs &r, Gate gate, int tch, int ncols) {
     constexpr int G = HopGroup<PREC>::value;
-    auto k = k_dslash_tm<PREC, DAG, RED, G>;
+    auto k = k_dslash_tm<PREC, DAG, RED, G, false, false, LF>;
     allow_lds(k, lds);
     hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols,
                        Halo{nullptr, nullptr, nullptr, 0, 0}, XrArgs{});
 }
 
-template <int PREC>
+template <int PREC, int LF = PREC>
 static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                       FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
     const int wvol = tm_wvol(g, PREC);
@@ -574,14 +579,14 @@ static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger
     if (red) r = *red;
     if (dagger) {
         if (red)
-            launch_tm_k<PREC, true, true>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, true, true, LF>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
         else
-            launch_tm_k<PREC, true, false>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, true, false, LF>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
     } else {
         if (red)
-            launch_tm_k<PREC, false, true>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, false, true, LF>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
         else
-            launch_tm_k<PREC, false, false>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
+            launch_tm_k<PREC, false, false, LF>(grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols);
     }
     // one partial per part of a brick slice: V / wvol of them per rhs
     if (red) launch_finalize(r, g.V / wvol, gate.batch ? gate.mode : -1, s);
@@ -589,13 +594,17 @@ static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger
 
 template <int PREC>
 static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
-                        FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
+                        FieldRef out, const RedArgs *red, Gate gate, hipStream_t s,
+                        const void *g12) {
     // the marching stencil writes one partial per workgroup: use it only
     // when the caller's partial buffer holds them (it always does when sized
     // by reduce_partials_cap)
     if (tm_eligible(g) && tm_fits<PREC>(g) && !g_force_site_kernel &&
         (!red || (int64_t)(g.V / tm_wvol(g, PREC)) * in.nrhs <= red->partials_cap)) {
-        launch_tm<PREC>(g, gauge, kappa, dagger, in, out, red, gate, s);
+        if (PREC == WD_F64 && g12)
+            launch_tm<WD_F64, kLinkF64R12>(g, g12, kappa, dagger, in, out, red, gate, s);
+        else
+            launch_tm<PREC>(g, gauge, kappa, dagger, in, out, red, gate, s);
         return;
     }
     const int nb = site_blocks(g.V);
@@ -618,11 +627,11 @@ static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagg
 }
 
 void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
-                   FieldRef out, const RedArgs *red, Gate gate, hipStream_t s) {
+                   FieldRef out, const RedArgs *red, Gate gate, hipStream_t s, const void *g12) {
     switch (in.prec) {
-        case WD_F64: launch_prec<WD_F64>(g, gauge, kappa, dagger, in, out, red, gate, s); break;
-        case WD_F32: launch_prec<WD_F32>(g, gauge, kappa, dagger, in, out, red, gate, s); break;
-        default: launch_prec<WD_F16>(g, gauge, kappa, dagger, in, out, red, gate, s); break;
+        case WD_F64: launch_prec<WD_F64>(g, gauge, kappa, dagger, in, out, red, gate, s, g12); break;
+        case WD_F32: launch_prec<WD_F32>(g, gauge, kappa, dagger, in, out, red, gate, s, nullptr); break;
+        default: launch_prec<WD_F16>(g, gauge, kappa, dagger, in, out, red, gate, s, nullptr); break;
     }
 }
 
@@ -640,7 +649,7 @@ bool dslash_xr_supported(const Geom &g, int prec, int nrhs, int partials_cap) {
     }
 }
 
-template <int PREC>
+template <int PREC, int LF = PREC>
 static bool xr_prec(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                     const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s) {
     if (!xr_ok<PREC>(g, in.nrhs, red.partials_cap)) return false;
@@ -653,12 +662,12 @@ static bool xr_prec(const Geom &g, const void *gauge, double kappa, int dagger, 
     constexpr int G = HopGroup<PREC>::value;
     const Halo nh{nullptr, nullptr, nullptr, 0, 0};
     if (dagger) {
-        auto k = k_dslash_tm<PREC, true, true, G, false, true>;
+        auto k = k_dslash_tm<PREC, true, true, G, false, true, LF>;
         allow_lds(k, lds);
         hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, FieldRef{}, kappa, red, gate, tch,
                            ncols, nh, xr);
     } else {
-        auto k = k_dslash_tm<PREC, false, true, G, false, true>;
+        auto k = k_dslash_tm<PREC, false, true, G, false, true, LF>;
         allow_lds(k, lds);
         hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, FieldRef{}, kappa, red, gate, tch,
                            ncols, nh, xr);
@@ -668,9 +677,13 @@ static bool xr_prec(const Geom &g, const void *gauge, double kappa, int dagger, 
 }
 
 bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
-                      const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s) {
+                      const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s,
+                      const void *g12) {
     switch (in.prec) {
-        case WD_F64: return xr_prec<WD_F64>(g, gauge, kappa, dagger, in, xr, red, gate, s);
+        case WD_F64:
+            if (g12)
+                return xr_prec<WD_F64, kLinkF64R12>(g, g12, kappa, dagger, in, xr, red, gate, s);
+            return xr_prec<WD_F64>(g, gauge, kappa, dagger, in, xr, red, gate, s);
         case WD_F32: return xr_prec<WD_F32>(g, gauge, kappa, dagger, in, xr, red, gate, s);
         default: return xr_prec<WD_F16>(g, gauge, kappa, dagger, in, xr, red, gate, s);
     }

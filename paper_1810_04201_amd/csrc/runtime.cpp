@@ -182,8 +182,10 @@ void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const 
     // the kernels compute in - kappa' * (hops): the +kappa sign is kappa' = -kappa
     kappa = -lat->hop_sign * kappa;
     static const char *names[3] = {"dslash_f64", "dslash_f32", "dslash_f16"};
+    // float64 on the lattice's own links: the 12-real form where it exists
+    const void *g12 = in.prec == WD_F64 && gauge == lat->gauge[WD_F64] ? lat->gauge12 : nullptr;
     timed(names[in.prec], s,
-          [&] { launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s); });
+          [&] { launch_dslash(lat->g, gauge, kappa, dagger, in, out, red, gate, s, g12); });
 }
 
 bool dslash_xr(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
@@ -191,9 +193,11 @@ bool dslash_xr(wd_lattice *lat, const void *gauge, double kappa, int dagger, con
     if (!dslash_xr_supported(lat->g, in.prec, in.nrhs, red.partials_cap)) return false;
     kappa = -lat->hop_sign * kappa;
     static const char *names[3] = {"dslash_xr_f64", "dslash_xr_f32", "dslash_xr_f16"};
+    const void *g12 = in.prec == WD_F64 && gauge == lat->gauge[WD_F64] ? lat->gauge12 : nullptr;
     bool ok = false;
-    timed(names[in.prec], s,
-          [&] { ok = launch_dslash_xr(lat->g, gauge, kappa, dagger, in, xr, red, gate, s); });
+    timed(names[in.prec], s, [&] {
+        ok = launch_dslash_xr(lat->g, gauge, kappa, dagger, in, xr, red, gate, s, g12);
+    });
     return ok;
 }
 
@@ -254,6 +258,7 @@ int wd_destroy_lattice(wd_lattice *lat) {
             if (lat->gauge_eo[p][q]) (void)hipFree(lat->gauge_eo[p][q]);
     }
     if (lat->halo_links) (void)hipFree(lat->halo_links);
+    if (lat->gauge12) (void)hipFree(lat->gauge12);
     delete lat;
     return WD_OK;
 }
@@ -264,9 +269,16 @@ int wd_lattice_volume(const wd_lattice *lat, int64_t *volume) {
     return WD_OK;
 }
 
+int wd_lattice_links_info(const wd_lattice *lat, int *f64_link_reals, double *su3_deviation) {
+    if (!lat) return fail(WD_ERR_ARG, "null lattice");
+    if (f64_link_reals) *f64_link_reals = lat->gauge12 ? 12 : 18;
+    if (su3_deviation) *su3_deviation = lat->su3_dev;
+    return WD_OK;
+}
+
 int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes) {
     if (!lat || !bytes) return fail(WD_ERR_ARG, "null argument");
-    size_t b = 0;
+    size_t b = lat->gauge12 ? gauge_bytes(kLinkF64R12, lat->g.V) : 0;
     for (int p = 0; p < 3; ++p) {
         if (lat->gauge[p]) b += gauge_bytes(p, lat->g.V);
         if (lat->gauge_eo[p][0]) b += 2 * gauge_bytes(p, lat->g.V / 2);
@@ -291,6 +303,39 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
         lat->gauge[WD_F64] = p;
     }
     launch_pack_gauge_f64(U, lat->gauge[WD_F64], lat->g, s);
+    // float64 links also stored as 12 reals when every link is special
+    // unitary to rounding (the marching stencil then reads 384 instead of
+    // 576 link bytes per site); WD_LINKS64_12=0 keeps 18 reals only
+    const char *e12 = getenv("WD_LINKS64_12");
+    const bool want12 = !(e12 && atoi(e12) == 0);
+    lat->su3_dev = -1.0;
+    if (want12) {
+        unsigned long long *dm = nullptr, hm = 0;
+        WD_HIP_CHECK(hipMallocAsync((void **)&dm, sizeof(hm), s));
+        (void)hipMemsetAsync(dm, 0, sizeof(hm), s);
+        launch_su3_check(lat->gauge[WD_F64], lat->g.V, dm, s);
+        (void)hipMemcpyAsync(&hm, dm, sizeof(hm), hipMemcpyDeviceToHost, s);
+        (void)hipFreeAsync(dm, s);
+        WD_LAUNCH_CHECK();
+        WD_HIP_CHECK(hipStreamSynchronize(s));
+        double dev;
+        memcpy(&dev, &hm, sizeof(dev));
+        lat->su3_dev = dev;
+    }
+    if (want12 && lat->su3_dev <= kSu3Tol) {
+        if (!lat->gauge12) {
+            void *p = nullptr;
+            hipError_t he = hipMalloc(&p, gauge_bytes(kLinkF64R12, lat->g.V));
+            if (he != hipSuccess)
+                return fail(WD_ERR_NOMEM, "hipMalloc of the F64-12 gauge form failed: %s",
+                            hipGetErrorString(he));
+            lat->gauge12 = p;
+        }
+        launch_gauge_lo(lat->gauge[WD_F64], lat->gauge12, kLinkF64R12, lat->g.V, s);
+    } else if (lat->gauge12) {
+        (void)hipFree(lat->gauge12);
+        lat->gauge12 = nullptr;
+    }
     for (int p = 1; p < 3; ++p)
         if (lat->gauge[p]) launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], p, lat->g.V, s);
     for (int p = 0; p < 3; ++p)

@@ -15,6 +15,8 @@
 struct wd_lattice {
     wd::Geom g{};
     void *gauge[3] = {nullptr, nullptr, nullptr};  // F64-18, F32-12, F16-12
+    void *gauge12 = nullptr;  // F64-12 beside F64-18 when the links are special unitary
+    double su3_dev = -1.0;    // largest row-2 deviation found by wd_set_gauge (-1: not checked)
     void *gauge_eo[3][2] = {};                     // even-odd halves [prec][parity]
     void *halo_links = nullptr;                    // U_t(x, -1) over face sites (t-slab)
     bool has_gauge = false;

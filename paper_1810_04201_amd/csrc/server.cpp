@@ -81,7 +81,10 @@ static bool eo_request(const wd_solve_params &p) { return (p.form & WD_SOLVE_EVE
 static size_t gauge_need(const wd_lattice *lat, const wd_solve_params &p, const bool form[3],
                          const bool eo[3]) {
     const int V = lat->g.V, prec = p.prec_inner;
-    size_t b = form[WD_F64] ? 0 : gauge_bytes(WD_F64, V);
+    // the float64 forms (F64-18, and F64-12 for special unitary links)
+    size_t b = form[WD_F64] ? 0
+                            : gauge_bytes(WD_F64, V) +
+                                  (lat->gauge12 ? gauge_bytes(kLinkF64R12, V) : 0);
     if (eo_request(p)) {
         if (!eo[WD_F64]) b += 2 * gauge_bytes(WD_F64, V / 2);
         if (prec != WD_F64 && !eo[prec]) b += 2 * gauge_bytes(prec, V / 2);

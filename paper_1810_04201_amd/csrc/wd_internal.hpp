@@ -45,6 +45,9 @@ namespace wd {
 //          F32-12: 12 planes of float4  (plane 3 mu + j: entries 2j, 2j+1 of
 //                  rows 0 and 1)
 //          F16-12: 12 planes of 2 x half2 (same entries, 8-byte elements)
+//          F64-12: 24 planes of double2 (plane 6 mu + k: entry k of rows 0
+//                  and 1); kept beside F64-18 when every link is special
+//                  unitary to rounding
 // Row 2 of the 12-real forms is rebuilt as conj(row0 x row1), which is exact
 // for special unitary links; the antiperiodic boundary sign is therefore
 // never folded into stored links but applied to the hop result.
@@ -60,8 +63,17 @@ __host__ __device__ inline size_t spinor_tile_bytes(int prec) {
 
 inline size_t spinor_bytes(int prec, int64_t n) { return tiles_of(n) * spinor_tile_bytes(prec); }
 
-inline size_t gauge_tile_bytes(int prec) {
-    return prec == WD_F64 ? 36u * 1024u : (prec == WD_F32 ? 12u * 1024u : 12u * 512u);
+// link form of float64 links stored as 12 reals (the other forms are named
+// by their precision)
+constexpr int kLinkF64R12 = 3;
+// largest |row 2 - conj(row 0 x row 1)| of a link that may be stored as 12
+// reals: a few hundred times the rounding of a special unitary matrix
+constexpr double kSu3Tol = 1e-14;
+
+inline size_t gauge_tile_bytes(int form) {
+    return form == WD_F64 ? 36u * 1024u
+                          : (form == WD_F32 ? 12u * 1024u
+                                            : (form == WD_F16 ? 12u * 512u : 24u * 1024u));
 }
 
 inline size_t gauge_bytes(int prec, int64_t V) { return tiles_of(V) * gauge_tile_bytes(prec); }
@@ -430,8 +442,12 @@ inline void choose_bricks(Geom &g) {
 
 // canonical float64 links -> F64-18 tiles (brick order)
 void launch_pack_gauge_f64(const double *canon, void *g64, const Geom &g, hipStream_t s);
-// F64-18 tiles -> 12-real F32 or F16 tiles
-void launch_gauge_lo(const void *g64, void *glo, int prec, int V, hipStream_t s);
+// F64-18 tiles -> 12-real F32, F16 or F64 (form kLinkF64R12) tiles
+void launch_gauge_lo(const void *g64, void *glo, int form, int V, hipStream_t s);
+// *maxbits = max(*maxbits, largest |row 2 - conj(row 0 x row 1)| over the
+// F64-18 links) as the bit pattern of a non-negative double (NaN counts as
+// infinity); *maxbits must be set beforehand
+void launch_su3_check(const void *g64, int V, unsigned long long *maxbits, hipStream_t s);
 
 // canonical [rhs][V][12] float64 <-> field (format conversion + reorder)
 void launch_import(const double *canon, FieldRef f, const Geom &g, hipStream_t s);
@@ -474,14 +490,18 @@ void launch_accum_zero(FieldRef x64, FieldRef xlo, Gate gate, hipStream_t s);
 
 // out = D in (dagger 0) or D^dag in (dagger 1); red != nullptr fuses the
 // reduction of |out|^2 with red->mode
+// g12: the F64-12 form of the same float64 links, read instead of gauge by
+// the marching stencil (nullptr: F64-18 only)
 void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
-                   FieldRef out, const RedArgs *red, Gate gate, hipStream_t s);
+                   FieldRef out, const RedArgs *red, Gate gate, hipStream_t s,
+                   const void *g12 = nullptr);
 // q = D in (or D^dag in) consumed where it is formed: x += alpha p,
 // r -= alpha q, |r|^2 reduced with red.mode (RED_RR) and finalised; q is not
 // stored.  Only the marching stencil does this: returns false (nothing
 // launched) where it does not run
 bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
-                      const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s);
+                      const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s,
+                      const void *g12 = nullptr);
 bool dslash_xr_supported(const Geom &g, int prec, int nrhs, int partials_cap);
 
 // x += alpha p ; r -= alpha Ap ; reduce |r|^2 (red.mode = RED_RR); active rhs

@@ -303,3 +303,60 @@ def test_full_size_sampled_parity(torch_dev, wd):
                                     dagger=bool(dagger))
         assert site_rel_err(got, wilson.to_real(want)) <= TOL[prec]
     lat.close()
+
+
+def test_f64_12_real_links_chosen_for_special_unitary(torch_dev, wd, monkeypatch):
+    """Special unitary links are also kept as 12 reals in float64 and the
+    float64 stencil reads them (results differ from the 18-real ones in the
+    last bits, both within 1e-13 of the oracle); WD_LINKS64_12=0 keeps
+    18 reals only.  Extra memory: the F64-12 form, 2/3 of F64-18."""
+    torch, dev = torch_dev
+    dims = (8, 8, 8, 8)
+    U = gauge(dims, 141, "exp")
+    psi = synth.gaussian_spinor(dims, 142)
+    want = wilson.apply_D(U, psi, dims, 0.1245)
+    outs = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("WD_LINKS64_12", mode)
+        lat = wd.Lattice(dims)
+        lat.set_gauge(torch.from_numpy(U).to(dev))
+        n, d = lat.links_info()
+        b18 = vol(dims) * 576
+        if mode == "1":
+            assert n == 12 and 0.0 <= d <= 1e-14
+            assert lat.gauge_bytes() == b18 + vol(dims) * 384
+        else:
+            assert n == 18 and d == -1.0
+            assert lat.gauge_bytes() == b18
+        pd = torch.from_numpy(psi).to(dev)
+        od = torch.full_like(pd, float("nan"))
+        lat.apply(0.1245, pd, od)
+        torch.cuda.synchronize()
+        outs[mode] = od.cpu().numpy()
+        lat.close()
+        assert site_rel_err(outs[mode], want) <= 1e-13
+    assert not np.array_equal(outs["1"], outs["0"])
+
+
+def test_f64_links_not_special_unitary_stay_18_real(torch_dev, wd):
+    """Links off the group (scaled by 1 + 1e-9, and random complex matrices)
+    fail the check: 18 reals only, and the stencil still matches the oracle
+    (a rebuilt row 2 would be wrong at O(1e-9) or O(1)).  A later
+    wd_set_gauge with special unitary links switches the form back on."""
+    torch, dev = torch_dev
+    dims = (4, 6, 8, 10)
+    rng = np.random.default_rng(143)
+    U = gauge(dims, 144, "exp")
+    psi = synth.gaussian_spinor(dims, 145)
+    lat = wd.Lattice(dims)
+    for Ux, n_want in ((U * (1 + 1e-9), 18), (rng.standard_normal(U.shape), 18), (U, 12)):
+        lat.set_gauge(torch.from_numpy(np.ascontiguousarray(Ux)).to(dev))
+        n, d = lat.links_info()
+        assert n == n_want, (n, d)
+        assert (d > 1e-14) == (n_want == 18)
+        pd = torch.from_numpy(psi).to(dev)
+        od = torch.full_like(pd, float("nan"))
+        lat.apply(0.1245, pd, od, dagger=1)
+        torch.cuda.synchronize()
+        assert site_rel_err(od.cpu().numpy(), wilson.apply_Ddag(Ux, psi, dims, 0.1245)) <= 1e-13
+    lat.close()
