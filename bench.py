@@ -498,6 +498,7 @@ def even_odd(args, wd, lat, bd, kappa, stream, torch, V):
         torch.cuda.synchronize()
         wd.wd_timing_enable(False)
         ms, _ = wd.wd_timing_read("eo_" + prec)
+        ms_xr, n_xr = wd.wd_timing_read("eo_xr_" + prec)
         it, up = info[0]["iters"], info[0]["reliable_updates"]
         res[f"{prec}_s"] = round(info[0]["seconds"], 3)
         res[f"{prec}_iters"] = it
@@ -505,18 +506,33 @@ def even_odd(args, wd, lat, bd, kappa, stream, torch, V):
         res[f"{prec}_rel_resid_D"] = info[0]["rel_resid_D"]
         # half-field launches that did work in this precision (gated launches
         # that found nothing to do are timed too, so the average is an upper
-        # bound): 4 per inner iteration; in float64 also b^ and M^dag b^ (3),
-        # 4 per reliable update after the first, and the odd half and the
-        # final residual (3)
-        n = 4 * it if prec != "f64" else 4 * it + 3 + 4 * max(up - 1, 0) + 3
+        # bound): 4 per inner iteration, the last of them x/r-updating when
+        # fused; in float64 also b^ and M^dag b^ (3), 4 per reliable update
+        # after the first, and the odd half and the final residual (3)
+        fused = n_xr > 0
+        n = (3 if fused else 4) * it
+        if prec == "f64":
+            n += 3 + 4 * max(up - 1, 0) + 3
+        # float64 halves are read as 12 reals when the links are special unitary
+        link = LINK_BYTES[prec]
+        if prec == "f64" and lat.links_info()[0] == 12:
+            link = 384
         if n:
             # one launch writes half the sites and reads every link once
             # (forward links of its parity, backward of the other) and the
             # other half's spinors; the c field some launches add is not counted
             avg = ms / n
-            per_site = 8 * LINK_BYTES[prec] // 4 + 2 * SPINOR_BYTES[prec]
+            per_site = 2 * link + 2 * SPINOR_BYTES[prec]
             res[f"hop_{prec}_avg_ms"] = round(avg, 4)
             res[f"hop_{prec}_GBps_algorithmic"] = round((V // 2) * per_site / avg / 1e6, 1)
+        if fused and it:
+            # plus c and p read, x and r (float64, else float32) read and
+            # written; q not stored
+            xs = 192 if prec == "f64" else 96
+            avg = ms_xr / it
+            per_site = 2 * link + 3 * SPINOR_BYTES[prec] + 4 * xs
+            res[f"hop_xr_{prec}_avg_ms"] = round(avg, 4)
+            res[f"hop_xr_{prec}_GBps_algorithmic"] = round((V // 2) * per_site / avg / 1e6, 1)
     log(f"even-odd: {res}")
     return res
 

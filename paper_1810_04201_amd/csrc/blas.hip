@@ -159,10 +159,13 @@ __global__ void k_gauge_split(const void *__restrict__ g, void *__restrict__ o, 
     }
 }
 
-void launch_gauge_split(const void *g64, void *half, int prec, int p, const Geom &geo,
+void launch_gauge_split(const void *g64, void *half, int form, int p, const Geom &geo,
                         hipStream_t s) {
     const dim3 gr(blocks_for(geo.V / 2, kBS)), bs(kBS);
-    if (prec == WD_F64)
+    const int prec = form;
+    if (form == kLinkF64R12)
+        hipLaunchKernelGGL(k_gauge_split<kLinkF64R12>, gr, bs, 0, s, g64, half, p, geo);
+    else if (prec == WD_F64)
         hipLaunchKernelGGL(k_gauge_split<WD_F64>, gr, bs, 0, s, g64, half, p, geo);
     else if (prec == WD_F32)
         hipLaunchKernelGGL(k_gauge_split<WD_F32>, gr, bs, 0, s, g64, half, p, geo);

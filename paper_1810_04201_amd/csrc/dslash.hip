@@ -115,7 +115,7 @@ __device__ __forceinline__ void su3_mul(const cx<R> u[9], const cx<R> h[3], cx<R
 }
 
 // one hop: project the neighbour spinor, multiply by the link, rebuild, add
-template <int MU, int S, bool BWD, int PREC>
+template <int MU, int S, bool BWD, int PREC, int LF = PREC>
 __device__ __forceinline__ void hop(const void *gauge, const FieldRef &in, int nbr_entry,
                                     int link_site, bool negate,
                                     cx<typename Spinor<PREC>::R> acc[12]) {
@@ -135,7 +135,7 @@ __device__ __forceinline__ void hop(const void *gauge, const FieldRef &in, int n
         }
     }
     cx<R> u[9];
-    Link<PREC>::load(gauge, MU, link_site, u);
+    Link<LF>::load(gauge, MU, link_site, u);
     cx<R> w0[3], w1[3];
     su3_mul<BWD>(u, h0, w0);
     su3_mul<BWD>(u, h1, w1);
@@ -696,11 +696,14 @@ bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger
 // parity, sit at their internal index >> 1.  Forward links come from the
 // parity-p half array gp, backward links U_mu(x - mu) from gq.  The hops are
 // summed in the order of the full stencil.
-template <int PREC, bool DAG, bool RED, bool HASC, int GROUP>
+// XR: the CG update x += alpha p, r -= alpha out_p in place of storing out
+// (the reduction is then |r|^2; with HASC and RED).  LF: the link form.
+template <int PREC, bool DAG, bool RED, bool HASC, int GROUP, bool XR = false, int LF = PREC>
 __global__ void __launch_bounds__(256) k_hop_half(Geom g, const void *__restrict__ gp,
                                                   const void *__restrict__ gq, int p, FieldRef in,
                                                   FieldRef c, FieldRef out, double k_d,
-                                                  double cs_d, RedArgs red, Gate gate) {
+                                                  double cs_d, RedArgs red, Gate gate,
+                                                  XrArgs xr) {
     using R = typename Spinor<PREC>::R;
     if (gate_off(gate)) return;  // grid-uniform
     const int nrhs = in.nrhs;
@@ -723,21 +726,21 @@ __global__ void __launch_bounds__(256) k_hop_half(Geom g, const void *__restrict
         constexpr int SB = -SF;
 #define WD_HOP_FENCE(k) \
     if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
-        hop<0, SF, false, PREC>(gp, fin, nb.xp >> 1, h, false, acc);
+        hop<0, SF, false, PREC, LF>(gp, fin, nb.xp >> 1, h, false, acc);
         WD_HOP_FENCE(1);
-        hop<0, SB, true, PREC>(gq, fin, nb.xm >> 1, nb.xm >> 1, false, acc);
+        hop<0, SB, true, PREC, LF>(gq, fin, nb.xm >> 1, nb.xm >> 1, false, acc);
         WD_HOP_FENCE(2);
-        hop<1, SF, false, PREC>(gp, fin, nb.yp >> 1, h, false, acc);
+        hop<1, SF, false, PREC, LF>(gp, fin, nb.yp >> 1, h, false, acc);
         WD_HOP_FENCE(3);
-        hop<1, SB, true, PREC>(gq, fin, nb.ym >> 1, nb.ym >> 1, false, acc);
+        hop<1, SB, true, PREC, LF>(gq, fin, nb.ym >> 1, nb.ym >> 1, false, acc);
         WD_HOP_FENCE(4);
-        hop<2, SF, false, PREC>(gp, fin, nb.zp >> 1, h, false, acc);
+        hop<2, SF, false, PREC, LF>(gp, fin, nb.zp >> 1, h, false, acc);
         WD_HOP_FENCE(5);
-        hop<2, SB, true, PREC>(gq, fin, nb.zm >> 1, nb.zm >> 1, false, acc);
+        hop<2, SB, true, PREC, LF>(gq, fin, nb.zm >> 1, nb.zm >> 1, false, acc);
         WD_HOP_FENCE(6);
-        hop<3, SF, false, PREC>(gp, fin, nb.tp >> 1, h, neg_tp, acc);
+        hop<3, SF, false, PREC, LF>(gp, fin, nb.tp >> 1, h, neg_tp, acc);
         WD_HOP_FENCE(7);
-        hop<3, SB, true, PREC>(gq, fin, nb.tm >> 1, nb.tm >> 1, neg_tm, acc);
+        hop<3, SB, true, PREC, LF>(gq, fin, nb.tm >> 1, nb.tm >> 1, neg_tm, acc);
         WD_HOP_FENCE(8);
 #undef WD_HOP_FENCE
         cx<R> o[12];
@@ -754,23 +757,27 @@ __global__ void __launch_bounds__(256) k_hop_half(Geom g, const void *__restrict
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             o[k] = o[k] - scale(kk, acc[k]);
-            if (RED) nrm += (double)o[k].re * (double)o[k].re + (double)o[k].im * (double)o[k].im;
+            if (RED && !XR)
+                nrm += (double)o[k].re * (double)o[k].re + (double)o[k].im * (double)o[k].im;
         }
-        Spinor<PREC>::store(rhs_view(out, rhs), h, o);
+        if constexpr (XR)
+            nrm = xr_site<PREC>(xr, rhs, h, (R)gate.st[rhs].alpha, o);
+        else
+            Spinor<PREC>::store(rhs_view(out, rhs), h, o);
     }
     if (RED) reduce_block(nrm, red.partials, (size_t)sb * nrhs + rhs);
 }
 
-template <int PREC, bool DAG, bool RED, bool HASC>
+template <int PREC, bool DAG, bool RED, bool HASC, int LF = PREC>
 static void launch_hop_half_k(dim3 grid, hipStream_t s, const Geom &g, const void *gp,
                               const void *gq, int p, FieldRef in, FieldRef c, FieldRef out,
                               double k, double cs, const RedArgs &r, Gate gate) {
     constexpr int G = HopGroup<PREC>::value;
-    hipLaunchKernelGGL((k_hop_half<PREC, DAG, RED, HASC, G>), grid, dim3(kSiteBlock), 0, s, g, gp,
-                       gq, p, in, c, out, k, cs, r, gate);
+    hipLaunchKernelGGL((k_hop_half<PREC, DAG, RED, HASC, G, false, LF>), grid, dim3(kSiteBlock),
+                       0, s, g, gp, gq, p, in, c, out, k, cs, r, gate, XrArgs{});
 }
 
-template <int PREC>
+template <int PREC, int LF = PREC>
 static void launch_hop_half_prec(const Geom &g, const void *gp, const void *gq, int p, double k,
                                  double cs, int dagger, FieldRef in, FieldRef c, FieldRef out,
                                  const RedArgs *red, Gate gate, hipStream_t s) {
@@ -781,23 +788,67 @@ static void launch_hop_half_prec(const Geom &g, const void *gp, const void *gq, 
     const bool hc = c.data != nullptr;
     const int sel = (dagger ? 4 : 0) | (red ? 2 : 0) | (hc ? 1 : 0);
     switch (sel) {
-        case 0: launch_hop_half_k<PREC, false, false, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 1: launch_hop_half_k<PREC, false, false, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 2: launch_hop_half_k<PREC, false, true, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 3: launch_hop_half_k<PREC, false, true, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 4: launch_hop_half_k<PREC, true, false, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 5: launch_hop_half_k<PREC, true, false, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 6: launch_hop_half_k<PREC, true, true, false>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        default: launch_hop_half_k<PREC, true, true, true>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 0: launch_hop_half_k<PREC, false, false, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 1: launch_hop_half_k<PREC, false, false, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 2: launch_hop_half_k<PREC, false, true, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 3: launch_hop_half_k<PREC, false, true, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 4: launch_hop_half_k<PREC, true, false, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 5: launch_hop_half_k<PREC, true, false, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 6: launch_hop_half_k<PREC, true, true, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        default: launch_hop_half_k<PREC, true, true, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
     }
     if (red) launch_finalize(r, nb, gate.batch ? gate.mode : -1, s);
 }
 
+template <int PREC, int LF = PREC>
+static void launch_hop_half_xr_prec(const Geom &g, const void *gp, const void *gq, int p,
+                                    double k, double cs, int dagger, FieldRef in, FieldRef c,
+                                    const XrArgs &xr, const RedArgs &red, Gate gate,
+                                    hipStream_t s) {
+    const int nb = site_blocks(xr.x.V);
+    const dim3 grid(nb * in.nrhs);
+    constexpr int G = HopGroup<PREC>::value;
+    if (dagger)
+        hipLaunchKernelGGL((k_hop_half<PREC, true, true, true, G, true, LF>), grid,
+                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.x, k, cs, red, gate, xr);
+    else
+        hipLaunchKernelGGL((k_hop_half<PREC, false, true, true, G, true, LF>), grid,
+                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.x, k, cs, red, gate, xr);
+    launch_finalize(red, nb, gate.batch ? gate.mode : -1, s);
+}
+
+void launch_hop_half_xr(const Geom &g, const void *gp, const void *gq, int p, double k, double cs,
+                        int dagger, FieldRef in, FieldRef c, const XrArgs &xr,
+                        const RedArgs &red, Gate gate, hipStream_t s, bool r12) {
+    switch (in.prec) {
+        case WD_F64:
+            if (r12)
+                launch_hop_half_xr_prec<WD_F64, kLinkF64R12>(g, gp, gq, p, k, cs, dagger, in, c,
+                                                              xr, red, gate, s);
+            else
+                launch_hop_half_xr_prec<WD_F64>(g, gp, gq, p, k, cs, dagger, in, c, xr, red, gate,
+                                                s);
+            break;
+        case WD_F32:
+            launch_hop_half_xr_prec<WD_F32>(g, gp, gq, p, k, cs, dagger, in, c, xr, red, gate, s);
+            break;
+        default:
+            launch_hop_half_xr_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, xr, red, gate, s);
+            break;
+    }
+}
+
 void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, double k, double cs,
                      int dagger, FieldRef in, FieldRef c, FieldRef out, const RedArgs *red,
-                     Gate gate, hipStream_t s) {
+                     Gate gate, hipStream_t s, bool r12) {
     switch (in.prec) {
-        case WD_F64: launch_hop_half_prec<WD_F64>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
+        case WD_F64:
+            if (r12)
+                launch_hop_half_prec<WD_F64, kLinkF64R12>(g, gp, gq, p, k, cs, dagger, in, c, out,
+                                                          red, gate, s);
+            else
+                launch_hop_half_prec<WD_F64>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s);
+            break;
         case WD_F32: launch_hop_half_prec<WD_F32>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
         default: launch_hop_half_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
     }

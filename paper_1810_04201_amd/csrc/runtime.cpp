@@ -88,7 +88,9 @@ bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[
     }
     if (!lat->gauge_eo[prec][0]) {
         void *h[2] = {nullptr, nullptr};
-        const size_t bytes = gauge_bytes(prec, lat->g.V / 2);
+        // float64 halves as 12 reals when the full-lattice links have that form
+        const int form = prec == WD_F64 && lat->gauge12 ? kLinkF64R12 : prec;
+        const size_t bytes = gauge_bytes(form, lat->g.V / 2);
         for (int p = 0; p < 2; ++p) {
             if (hipMalloc(&h[p], bytes) != hipSuccess) {
                 if (h[0]) (void)hipFree(h[0]);
@@ -96,7 +98,7 @@ bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[
                 return false;
             }
         }
-        for (int p = 0; p < 2; ++p) launch_gauge_split(lat->gauge[WD_F64], h[p], prec, p, lat->g, s);
+        for (int p = 0; p < 2; ++p) launch_gauge_split(lat->gauge[WD_F64], h[p], form, p, lat->g, s);
         // other streams (server slots) may use the form next: finish building it
         if (hipStreamSynchronize(s) != hipSuccess) {
             (void)hipFree(h[0]);
@@ -106,6 +108,7 @@ bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[
         }
         lat->gauge_eo[prec][0] = h[0];
         lat->gauge_eo[prec][1] = h[1];
+        if (prec == WD_F64) lat->eo64_r12 = form == kLinkF64R12;
     }
     out[0] = lat->gauge_eo[prec][0];
     out[1] = lat->gauge_eo[prec][1];
@@ -207,8 +210,21 @@ void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs
     // D_{p,1-p} = hop_sign * kappa * H_{p,1-p}; the kernel computes cs c - k H in
     const double k = -lat->hop_sign * kappa;
     static const char *names[3] = {"eo_f64", "eo_f32", "eo_f16"};
+    const bool r12 = in.prec == WD_F64 && lat->eo64_r12 && gh[0] == lat->gauge_eo[WD_F64][0];
     timed(names[in.prec], s, [&] {
-        launch_hop_half(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, out, red, gate, s);
+        launch_hop_half(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, out, red, gate, s, r12);
+    });
+}
+
+void hop_half_xr(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
+                 const FieldRef &in, const FieldRef &c, const XrArgs &xr, const RedArgs &red,
+                 Gate gate, hipStream_t s) {
+    const double k = -lat->hop_sign * kappa;
+    static const char *names[3] = {"eo_xr_f64", "eo_xr_f32", "eo_xr_f16"};
+    const bool r12 = in.prec == WD_F64 && lat->eo64_r12 && gh[0] == lat->gauge_eo[WD_F64][0];
+    timed(names[in.prec], s, [&] {
+        launch_hop_half_xr(lat->g, gh[p], gh[1 - p], p, k, cs, dagger, in, c, xr, red, gate, s,
+                           r12);
     });
 }
 
@@ -281,7 +297,8 @@ int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes) {
     size_t b = lat->gauge12 ? gauge_bytes(kLinkF64R12, lat->g.V) : 0;
     for (int p = 0; p < 3; ++p) {
         if (lat->gauge[p]) b += gauge_bytes(p, lat->g.V);
-        if (lat->gauge_eo[p][0]) b += 2 * gauge_bytes(p, lat->g.V / 2);
+        if (lat->gauge_eo[p][0])
+            b += 2 * gauge_bytes(p == WD_F64 && lat->eo64_r12 ? kLinkF64R12 : p, lat->g.V / 2);
     }
     if (lat->halo_links) b += gauge_bytes(WD_F64, lat->g.V / lat->g.L[3]);
     *bytes = b;
@@ -338,10 +355,18 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
     }
     for (int p = 1; p < 3; ++p)
         if (lat->gauge[p]) launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], p, lat->g.V, s);
+    // float64 halves whose form no longer matches are dropped (rebuilt on use)
+    if (lat->gauge_eo[WD_F64][0] && lat->eo64_r12 != (lat->gauge12 != nullptr)) {
+        for (int q = 0; q < 2; ++q) {
+            (void)hipFree(lat->gauge_eo[WD_F64][q]);
+            lat->gauge_eo[WD_F64][q] = nullptr;
+        }
+    }
     for (int p = 0; p < 3; ++p)
         for (int q = 0; q < 2; ++q)
             if (lat->gauge_eo[p][q])
-                launch_gauge_split(lat->gauge[WD_F64], lat->gauge_eo[p][q], p, q, lat->g, s);
+                launch_gauge_split(lat->gauge[WD_F64], lat->gauge_eo[p][q],
+                                   p == WD_F64 && lat->eo64_r12 ? kLinkF64R12 : p, q, lat->g, s);
     WD_LAUNCH_CHECK();
     WD_HIP_CHECK(hipStreamSynchronize(s));
     lat->has_gauge = true;

@@ -17,6 +17,7 @@ struct wd_lattice {
     void *gauge[3] = {nullptr, nullptr, nullptr};  // F64-18, F32-12, F16-12
     void *gauge12 = nullptr;  // F64-12 beside F64-18 when the links are special unitary
     double su3_dev = -1.0;    // largest row-2 deviation found by wd_set_gauge (-1: not checked)
+    bool eo64_r12 = false;    // gauge_eo[WD_F64] holds the F64-12 form
     void *gauge_eo[3][2] = {};                     // even-odd halves [prec][parity]
     void *halo_links = nullptr;                    // U_t(x, -1) over face sites (t-slab)
     bool has_gauge = false;
@@ -71,6 +72,12 @@ bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[
 void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
               const FieldRef &in, const FieldRef &c, const FieldRef &out, const RedArgs *red,
               Gate gate, hipStream_t s);
+
+// hop_half with c present whose output q is consumed where it is formed
+// (x += alpha p, r -= alpha q; see launch_hop_half_xr)
+void hop_half_xr(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
+                 const FieldRef &in, const FieldRef &c, const XrArgs &xr, const RedArgs &red,
+                 Gate gate, hipStream_t s);
 
 // stencil launch with optional event timing
 void dslash(wd_lattice *lat, const void *gauge, double kappa, int dagger, const FieldRef &in,
@@ -130,6 +137,7 @@ class Solve {
     void enqueue_reliable();
     void op(bool first, const FieldRef &in, const FieldRef &out, const RedArgs *red, Gate gate,
             bool lo);
+    bool op_xr(const FieldRef &in, const RedArgs &rr, Gate gate);
     void enqueue_finish();
     int push_status();
     RedArgs red(int mode) const;

@@ -86,7 +86,7 @@ static size_t gauge_need(const wd_lattice *lat, const wd_solve_params &p, const 
                             : gauge_bytes(WD_F64, V) +
                                   (lat->gauge12 ? gauge_bytes(kLinkF64R12, V) : 0);
     if (eo_request(p)) {
-        if (!eo[WD_F64]) b += 2 * gauge_bytes(WD_F64, V / 2);
+        if (!eo[WD_F64]) b += 2 * gauge_bytes(lat->gauge12 ? kLinkF64R12 : WD_F64, V / 2);
         if (prec != WD_F64 && !eo[prec]) b += 2 * gauge_bytes(prec, V / 2);
     } else if (prec != WD_F64 && !form[prec]) {
         b += gauge_bytes(prec, V);

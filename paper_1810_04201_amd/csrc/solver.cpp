@@ -209,10 +209,11 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     use_graph_ = s_ != nullptr && !timing_enabled() && !(ge && atoi(ge) == 0);
     // A^dag (A p) formed where x and r are updated (q never stored): 2 of
     // the 9 field transfers of an iteration's vector updates saved.  The
-    // marching stencil on the full lattice only; WD_FUSE_XR=0 turns it off.
+    // marching stencil on the full lattice, the half-field stencil's second
+    // launch on the even-odd form; WD_FUSE_XR=0 turns it off.
     const char *fx = getenv("WD_FUSE_XR");
-    fuse_xr_ = !eo_ && !(fx && atoi(fx) == 0) &&
-               dslash_xr_supported(lat_->g, prec_, nrhs, partials_cap_);
+    fuse_xr_ = !(fx && atoi(fx) == 0) &&
+               (eo_ || dslash_xr_supported(lat_->g, prec_, nrhs, partials_cap_));
     return WD_OK;
 }
 
@@ -243,6 +244,17 @@ void Solve::op(bool first, const FieldRef &in, const FieldRef &out, const RedArg
     const FieldRef &tmp = lo ? tmpl_ : tmp64_;
     hop_half(lat_, gh, 1, k, 0.0, dag, in, FieldRef{}, tmp, nullptr, gate, s_);  // D_oe in
     hop_half(lat_, gh, 0, -k, 1.0, dag, tmp, in, out, red, gate, s_);           // in - D_eo tmp
+}
+
+// The second operator application of an iteration on in = A p, with the
+// x/r update fused into its last launch; false if nothing was launched
+bool Solve::op_xr(const FieldRef &in, const RedArgs &rr, Gate gate) {
+    const double k = p_.kappa;
+    const XrArgs xr{xl_, rl_, pl_};
+    if (!eo_) return dslash_xr(lat_, gauge_lo_, k, d2_, in, xr, rr, gate, s_);
+    hop_half(lat_, ghlo_, 1, k, 0.0, d2_, in, FieldRef{}, tmpl_, nullptr, gate, s_);
+    hop_half_xr(lat_, ghlo_, 0, -k, 1.0, d2_, tmpl_, in, xr, rr, gate, s_);
+    return true;
 }
 
 int Solve::start() {
@@ -294,8 +306,7 @@ void Solve::enqueue_inner(int iters) {
     RedArgs rr = red(RED_RR);
     for (int i = 0; i < iters; ++i) {
         op(true, pl_, tl_, &ra, g, true);
-        if (!fuse_xr_ || !dslash_xr(lat_, gauge_lo_, p_.kappa, d2_, tl_, XrArgs{xl_, rl_, pl_},
-                                    rr, g, s_)) {
+        if (!fuse_xr_ || !op_xr(tl_, rr, g)) {
             op(false, tl_, apl_, nullptr, g, true);
             launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
         }

@@ -456,8 +456,8 @@ void launch_export(FieldRef f, double *canon, const Geom &g, hipStream_t s);
 void launch_convert(FieldRef src, FieldRef dst, Gate gate, hipStream_t s);
 void launch_zero(FieldRef f, hipStream_t s);
 // even-odd halves (V / 2 sites each, parity p): links of the parity-p sites
-// from the F64-18 tiles, in the half layout and format prec
-void launch_gauge_split(const void *g64, void *half, int prec, int p, const Geom &g,
+// from the F64-18 tiles, in the half layout and link form `form`
+void launch_gauge_split(const void *g64, void *half, int form, int p, const Geom &g,
                         hipStream_t s);
 // canonical [rhs][V][12] float64 <-> half field of parity p (sites of the
 // other parity untouched on export)
@@ -465,10 +465,17 @@ void launch_import_half(const double *canon, FieldRef f, int p, const Geom &g, h
 void launch_export_half(FieldRef f, double *canon, int p, const Geom &g, hipStream_t s);
 // out_p = cs * c_p - k * H_{p,1-p} in_{1-p} on half fields (H the hopping
 // sum of Eq. (1), projectors exchanged for dagger; c.data == nullptr: no
-// c term), links gp of parity p and gq of parity 1 - p; red fuses |out|^2
+// c term), links gp of parity p and gq of parity 1 - p; red fuses |out|^2;
+// r12: float64 halves in the F64-12 form
 void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, double k,
                      double cs, int dagger, FieldRef in, FieldRef c, FieldRef out,
-                     const RedArgs *red, Gate gate, hipStream_t s);
+                     const RedArgs *red, Gate gate, hipStream_t s, bool r12 = false);
+// the same with c present and its output q consumed where it is formed:
+// x += alpha p, r -= alpha q (XrArgs on half fields), |r|^2 reduced with
+// red.mode and finalised; q is not stored
+void launch_hop_half_xr(const Geom &g, const void *gp, const void *gq, int p, double k,
+                        double cs, int dagger, FieldRef in, FieldRef c, const XrArgs &xr,
+                        const RedArgs &red, Gate gate, hipStream_t s, bool r12 = false);
 
 // halo exchange (float64): the two faces of in for the neighbouring slabs
 // (to_prev: (1 -+ gamma_t) psi(x, 0) for its forward hop; to_next: the

@@ -214,3 +214,65 @@ def test_evenodd_served_equals_alone(env):
     torch.cuda.synchronize()
     assert rc2 == 0 and torch.equal(xa, xs)
     lat.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f16"])
+def test_evenodd_fused_update_and_link_forms(env, monkeypatch, prec):
+    """The even-odd iteration's last half-field launch updates x and r where
+    it forms q (WD_FUSE_XR=0: q stored, separate update), on float64 halves
+    of 12 or 18 reals (WD_LINKS64_12).  Every combination reaches the
+    oracle's solution; the fused runs launch the x/r-updating kernel."""
+    torch, dev, wd = env
+    dims = (4, 6, 8, 10)
+    U = gauge(dims, 151)
+    b = synth.gaussian_spinor(dims, 152)
+    xo, _, oinfo = evenodd.solve(U, b, dims, 0.124, tol=1e-12)
+    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+    _, it, _ = evenodd.solve(U, b, dims, 0.124, tol=1e-10)
+    for fuse in ("1", "0"):
+        for r12 in ("1", "0"):
+            monkeypatch.setenv("WD_FUSE_XR", fuse)
+            monkeypatch.setenv("WD_LINKS64_12", r12)
+            print(f"eo fuse={fuse} r12={r12} prec={prec}", flush=True)
+            lat = wd.Lattice(dims)
+            lat.set_gauge(torch.from_numpy(U).to(dev))
+            assert lat.links_info()[0] == (12 if r12 == "1" else 18)
+            bd = torch.from_numpy(b).to(dev)
+            xd = torch.zeros_like(bd)
+            wd.wd_timing_reset()
+            wd.wd_timing_enable(True)
+            rc, info = lat.solve(bd, xd, 0.124, tol=1e-10, prec=prec, even_odd=True)
+            torch.cuda.synchronize()
+            wd.wd_timing_enable(False)
+            assert rc == 0 and info[0]["true_rel_resid"] <= 1e-10
+            assert (wd.wd_timing_read("eo_xr_" + prec)[1] > 0) == (fuse == "1")
+            assert rel(xd.cpu().numpy(), xo) <= max(1e-9, 2e-10 * cond)
+            if prec == "f64":
+                assert abs(info[0]["iters"] - it) <= 1
+            lat.close()
+
+
+def test_schur_after_gauge_form_changes(env):
+    """Float64 halves built on special unitary links (12 reals) are dropped
+    and rebuilt with 18 when wd_set_gauge gets links off the group, and
+    back: M stays equal to the oracle's in every case."""
+    torch, dev, wd = env
+    dims = (4, 4, 4, 8)
+    U = gauge(dims, 153)
+    psi = synth.gaussian_spinor(dims, 154)
+    lat = wd.Lattice(dims)
+    bytes_seen = []
+    for Ux, n in ((U, 12), (U * (1 + 1e-9), 18), (U, 12)):
+        lat.set_gauge(torch.from_numpy(np.ascontiguousarray(Ux)).to(dev))
+        assert lat.links_info()[0] == n
+        pd = torch.from_numpy(psi).to(dev)
+        od = torch.full_like(pd, float("nan"))
+        lat.apply_schur(0.1245, pd, od, prec="f64")
+        torch.cuda.synchronize()
+        _check_schur(od.cpu().numpy(), Ux, psi, dims, 0.1245, "f64", 0)
+        bytes_seen.append(lat.gauge_bytes())
+    lat.close()
+    V = vol(dims)
+    # F64-18 + F64-12 + 12-real halves; F64-18 + 18-real halves
+    assert bytes_seen[0] == bytes_seen[2] == V * 576 + V * 384 + V * 384
+    assert bytes_seen[1] == V * 576 + V * 576
