@@ -39,12 +39,12 @@ FLOP_PER_SITE = 1320
 # four links per site (each read once), spinor out once
 BYTES_PER_SITE = {"f64": 192 + 576 + 192, "f32": 96 + 192 + 96, "f16": 52 + 96 + 52}
 LINK_BYTES = {"f64": 576, "f32": 192, "f16": 96}
-# the CG's second stencil with the x/r update fused: links and spinor in as
-# above, p read, x and r read and written (F64, or F32 beside F32/F16 p and
-# q); q itself is never stored
-XR_BYTES_PER_SITE = {"f64": 576 + 192 + 192 + 2 * 192 + 2 * 192,
-                     "f32": 192 + 96 + 96 + 2 * 96 + 2 * 96,
-                     "f16": 96 + 52 + 52 + 2 * 96 + 2 * 96}
+# the CG's second stencil with the r update fused: links and spinor in as
+# above, r read and written (F64, or F32 beside an F32/F16 stencil); q itself
+# is never stored (x follows in the p update)
+XR_BYTES_PER_SITE = {"f64": 576 + 192 + 2 * 192,
+                     "f32": 192 + 96 + 2 * 96,
+                     "f16": 96 + 52 + 2 * 96}
 FUSED_XR = os.environ.get("WD_FUSE_XR", "1") != "0"
 # the slab stencil reads float64 links as 18 reals
 HALO_BYTES_PER_SITE = 192 + 576 + 192
@@ -56,7 +56,7 @@ def f64_bytes(lat):
     bytes per site) when wd_set_gauge found them special unitary, else 18
     (576)."""
     link = 384 if lat.links_info()[0] == 12 else 576
-    return 192 + link + 192, link + 192 + 192 + 2 * 192 + 2 * 192
+    return 192 + link + 192, link + 192 + 2 * 192
 SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52}
 HBM_PEAK_GBS = 8000.0
 METRIC = "dslash GFLOP/s & HBM GB/s; CG time-to-1e-10 residual, mixed vs FP64"
@@ -241,7 +241,7 @@ def main():
     # dominant kernel: whichever FP64 stencil kernel took the most time
     if FUSED_XR and apps["xr_f64"] and ms["xr_f64"] > ms["f64"]:
         roofline = roof("xr_f64", f"dslash_xr_f64 (k_dslash_tm<F64, XR>, time-marching stencil "
-                                  f"with the fused CG update x += alpha p, r -= alpha D^dag D p, "
+                                  f"with the fused CG update r -= alpha D^dag D p, "
                                   f"F64-{f64_link_reals} links)")
         roofline["plain_stencil"] = plain
     else:
@@ -526,11 +526,11 @@ def even_odd(args, wd, lat, bd, kappa, stream, torch, V):
             res[f"hop_{prec}_avg_ms"] = round(avg, 4)
             res[f"hop_{prec}_GBps_algorithmic"] = round((V // 2) * per_site / avg / 1e6, 1)
         if fused and it:
-            # plus c and p read, x and r (float64, else float32) read and
-            # written; q not stored
+            # plus c read, r (float64, else float32) read and written; q not
+            # stored
             xs = 192 if prec == "f64" else 96
             avg = ms_xr / it
-            per_site = 2 * link + 3 * SPINOR_BYTES[prec] + 4 * xs
+            per_site = 2 * link + 2 * SPINOR_BYTES[prec] + 2 * xs
             res[f"hop_xr_{prec}_avg_ms"] = round(avg, 4)
             res[f"hop_xr_{prec}_GBps_algorithmic"] = round((V // 2) * per_site / avg / 1e6, 1)
     log(f"even-odd: {res}")

@@ -285,9 +285,12 @@ __global__ void k_zero(FieldRef f) {
 }
 
 // x64 += xlo ; xlo = 0 for the rhs a reliable update takes (GATE_TRIGGER),
-// else for every rhs not yet converged
-template <int PL>
-__global__ void k_accum_zero(FieldRef x, FieldRef xl, Gate gate) {
+// else for every rhs not yet converged.  An rhs whose last alpha p is still
+// pending (it froze between the r update and the lagged x update) adds it:
+// x64 += xlo + alpha p, in float64.
+template <int PL, int PP>
+__global__ void __launch_bounds__(kSiteBlock) k_accum_zero(FieldRef x, FieldRef xl, FieldRef p,
+                                                         Gate gate) {
     const int r = blockIdx.y;
     if (gate.mode == GATE_TRIGGER) {
         if (gate_off(gate) || !gate_rhs(gate, r)) return;
@@ -297,16 +300,25 @@ __global__ void k_accum_zero(FieldRef x, FieldRef xl, Gate gate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= x.V) return;
     const FieldRef xv = rhs_view(x, r), lv = rhs_view(xl, r);
-    cx<double> a[12], b[12], z[12];
-    load_as_double<WD_F64>(xv, i, a);
+    cx<double> b[12];
     load_as_double<PL>(lv, i, b);
+    if (gate.st[r].pend) {
+        const double alpha = gate.st[r].alpha;
+        cx<double> q[12];
+        load_as_double<PP>(rhs_view(p, r), i, q);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        a[k] = a[k] + b[k];
-        z[k] = {0.0, 0.0};
+        for (int k = 0; k < 12; ++k) b[k] = {b[k].re + alpha * q[k].re, b[k].im + alpha * q[k].im};
     }
-    store_from_double<WD_F64>(xv, i, a);
-    store_from_double<PL>(lv, i, z);
+    {
+        cx<double> a[12];
+        load_as_double<WD_F64>(xv, i, a);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) b[k] = a[k] + b[k];
+    }
+    store_from_double<WD_F64>(xv, i, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) b[k] = {0.0, 0.0};
+    store_from_double<PL>(lv, i, b);
 }
 
 #define WD_DISPATCH_PREC(P, ...)                   \
@@ -355,9 +367,14 @@ void launch_zero(FieldRef f, hipStream_t s) {
                      hipLaunchKernelGGL(k_zero<PP>, field_grid(f), dim3(kSiteBlock), 0, s, f));
 }
 
-void launch_accum_zero(FieldRef x, FieldRef xl, Gate gate, hipStream_t s) {
-    WD_DISPATCH_PREC(xl.prec, hipLaunchKernelGGL(k_accum_zero<PP>, field_grid(x),
-                                                 dim3(kSiteBlock), 0, s, x, xl, gate));
+void launch_accum_zero(FieldRef x, FieldRef xl, FieldRef p, Gate gate, hipStream_t s) {
+    const dim3 gr = field_grid(x), bs(kSiteBlock);
+    if (xl.prec == WD_F64)
+        hipLaunchKernelGGL((k_accum_zero<WD_F64, WD_F64>), gr, bs, 0, s, x, xl, p, gate);
+    else if (p.prec == WD_F32)
+        hipLaunchKernelGGL((k_accum_zero<WD_F32, WD_F32>), gr, bs, 0, s, x, xl, p, gate);
+    else
+        hipLaunchKernelGGL((k_accum_zero<WD_F32, WD_F16>), gr, bs, 0, s, x, xl, p, gate);
 }
 
 // ------------------------------------------------------------------ CG updates
@@ -367,8 +384,8 @@ void launch_accum_zero(FieldRef x, FieldRef xl, Gate gate, hipStream_t s) {
 // type of PX, the norm in float64.  A frozen rhs's workgroups return at once
 // (the finaliser ignores its partials).
 template <int PX, int PPP>
-__global__ void k_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, RedArgs red,
-                            Gate gate) {
+__global__ void __launch_bounds__(kSiteBlock) k_update_xr(FieldRef x, FieldRef r, FieldRef p,
+                                                        FieldRef Ap, RedArgs red, Gate gate) {
     if (gate_off(gate)) return;
     const int rhs = blockIdx.y;
     if (!gate_rhs(gate, rhs)) return;
@@ -423,6 +440,47 @@ __global__ void k_update_p(FieldRef p, FieldRef r, Gate gate) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) o[k] = {(typename Spinor<PPP>::R)pv[k].re, (typename Spinor<PPP>::R)pv[k].im};
     Spinor<PPP>::store(pf, i, o);
+}
+
+// x += alpha p ; p = r + beta p: the x update of the iteration whose r
+// update a stencil did, merged with the p update (p read once).  Same
+// arithmetic as k_update_xr's x update and k_update_p.
+template <int PX, int PPP>
+__global__ void k_update_xp(FieldRef x, FieldRef p, FieldRef r, Gate gate) {
+    if (gate_off(gate)) return;
+    const int rhs = blockIdx.y;
+    if (!gate_rhs(gate, rhs)) return;
+    const RhsState &st = gate.st[rhs];
+    using R = typename Spinor<PX>::R;
+    using RP = typename Spinor<PPP>::R;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.V) return;
+    const FieldRef xf = rhs_view(x, rhs), pf = rhs_view(p, rhs);
+    const R alpha = (R)st.alpha, beta = (R)st.beta;
+    cx<RP> q[12];
+    cx<R> v[12];
+    Spinor<PPP>::load(pf, i, q);
+    Spinor<PX>::load(xf, i, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        v[k] = {v[k].re + alpha * (R)q[k].re, v[k].im + alpha * (R)q[k].im};
+    Spinor<PX>::store(xf, i, v);
+    Spinor<PX>::load(rhs_view(r, rhs), i, v);
+    cx<RP> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        o[k] = {(RP)(v[k].re + beta * (R)q[k].re), (RP)(v[k].im + beta * (R)q[k].im)};
+    Spinor<PPP>::store(pf, i, o);
+}
+
+void launch_update_xp(FieldRef x, FieldRef p, FieldRef r, Gate gate, hipStream_t s) {
+    const dim3 gr = field_grid(p), bs(kSiteBlock);
+    if (x.prec == WD_F64)
+        hipLaunchKernelGGL((k_update_xp<WD_F64, WD_F64>), gr, bs, 0, s, x, p, r, gate);
+    else if (p.prec == WD_F32)
+        hipLaunchKernelGGL((k_update_xp<WD_F32, WD_F32>), gr, bs, 0, s, x, p, r, gate);
+    else
+        hipLaunchKernelGGL((k_update_xp<WD_F32, WD_F16>), gr, bs, 0, s, x, p, r, gate);
 }
 
 void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const RedArgs &red,

@@ -342,6 +342,7 @@ __device__ inline void finalize_rhs(const RedArgs &red, int r, double total) {
                 if (trig) {
                     st.active = 0;
                     st.trigger = 1;
+                    st.pend = c.lag_x;  // its last alpha p is not in x_lo yet
                 }
             }
             break;
@@ -350,6 +351,7 @@ __device__ inline void finalize_rhs(const RedArgs &red, int r, double total) {
                 st.rr_true = total;
                 st.updates += 1;
                 st.trigger = 0;
+                st.pend = 0;  // added to x by the update's accumulation
                 if (!finite(total)) {
                     st.failed = WD_ERR_NUMERIC;
                     st.active = 0;
@@ -372,6 +374,7 @@ __device__ inline void finalize_rhs(const RedArgs &red, int r, double total) {
         case RED_B0:
             st.rr0 = total;
             st.restarted = 0;
+            st.pend = 0;
             st.active = 0;
             st.converged = 0;
             st.failed = 0;

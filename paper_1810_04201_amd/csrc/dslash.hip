@@ -46,6 +46,12 @@
 #ifndef WD_NT_OUT
 #define WD_NT_OUT 1
 #endif
+// the marching stencil's fused r update: load r at the start of the step
+// (its latency hidden behind the hops) instead of after them; per
+// precision bit: 1 float64, 2 float32, 4 binary16
+#ifndef WD_XR_PREFETCH
+#define WD_XR_PREFETCH 1
+#endif
 
 namespace wd {
 
@@ -303,32 +309,35 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
     if (RED) reduce_block(nrm, red.partials, (size_t)sb * nrhs + rhs);
 }
 
-// x += alpha p, r -= alpha q at site i of one rhs (x, r in F64, or F32 beside
-// F32/F16 p), in the compute type of the stencil; returns |r|^2 in float64.
+// r -= alpha q at site i of one rhs (r in F64, or F32 beside an F32/F16
+// stencil), in the compute type of the stencil; returns |r|^2 in float64.
 // The same arithmetic as the stand-alone update of the solver, on the
-// stencil's unrounded q.
+// stencil's unrounded q.  xr_site_r: with r already loaded into v.
 template <int PREC>
-__device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
-                                          typename Spinor<PREC>::R alpha,
-                                          const cx<typename Spinor<PREC>::R> q[12]) {
+__device__ __forceinline__ double xr_site_r(const XrArgs &a, int rhs, int i,
+                                            typename Spinor<PREC>::R alpha,
+                                            const cx<typename Spinor<PREC>::R> q[12],
+                                            cx<typename Spinor<PREC>::R> v[12]) {
     constexpr int PX = PREC == WD_F64 ? WD_F64 : WD_F32;
-    using R = typename Spinor<PREC>::R;
-    const FieldRef xf = rhs_view(a.x, rhs), rf = rhs_view(a.r, rhs);
-    cx<R> v[12], w[12];
-    Spinor<PREC>::load(rhs_view(a.p, rhs), i, w);
-    Spinor<PX>::load(xf, i, v);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) v[k] = {v[k].re + alpha * w[k].re, v[k].im + alpha * w[k].im};
-    Spinor<PX>::template store<WD_NT_OUT>(xf, i, v);
-    Spinor<PX>::load(rf, i, v);
     double nrm = 0.0;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         v[k] = {v[k].re - alpha * q[k].re, v[k].im - alpha * q[k].im};
         nrm += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
     }
-    Spinor<PX>::template store<WD_NT_OUT>(rf, i, v);
+    Spinor<PX>::template store<WD_NT_OUT>(rhs_view(a.r, rhs), i, v);
     return nrm;
+}
+
+template <int PREC>
+__device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
+                                          typename Spinor<PREC>::R alpha,
+                                          const cx<typename Spinor<PREC>::R> q[12]) {
+    constexpr int PX = PREC == WD_F64 ? WD_F64 : WD_F32;
+    using R = typename Spinor<PREC>::R;
+    cx<R> v[12];
+    Spinor<PX>::load(rhs_view(a.r, rhs), i, v);
+    return xr_site_r<PREC>(a, rhs, i, alpha, q, v);
 }
 
 // Time-marching stencil.  One workgroup per brick column, chunk of time
@@ -356,8 +365,8 @@ __device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
 // sources of the prologue's spinor and link, of the last step's slice copy,
 // and the boundary sign change.
 // XR: the CG update that consumes q = A p is done where q is formed, so q is
-// never stored: x += alpha p, r -= alpha q, and the reduction is |r|^2 (see
-// XrArgs).  out is unused.
+// never stored: r -= alpha q, and the reduction is |r|^2 (see XrArgs).  out
+// is unused.
 // LF: the link form (PREC's own, or F64-12 for float64; not with HALO).
 template <int PREC, bool DAG, bool RED, int GROUP, bool HALO = false, bool XR = false,
           int LF = PREC>
@@ -446,6 +455,10 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
                          next_from_halo ? fbase >> 6 : (cbase + tn * bvol) >> 6, (char *)nxt.data);
         const int sbase = cbase + t * bvol;
         const int i = sbase + l;
+        constexpr bool XPRE = XR && ((WD_XR_PREFETCH >> PREC) & 1);
+        cx<R> rpre[XPRE ? 12 : 1];
+        if constexpr (XPRE)
+            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::load(rhs_view(xr.r, rhs), i, rpre);
         const Nbrs nb = neighbours(g, i);
         cx<R> acc[12];
 #pragma unroll
@@ -493,7 +506,9 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
             if (RED && !XR)
                 nrm += (double)c[k].re * (double)c[k].re + (double)c[k].im * (double)c[k].im;
         }
-        if (XR)
+        if constexpr (XPRE)
+            nrm = xr_site_r<PREC>(xr, rhs, i, (R)gate.st[rhs].alpha, c, rpre);
+        else if constexpr (XR)
             nrm = xr_site<PREC>(xr, rhs, i, (R)gate.st[rhs].alpha, c);
         else
             Spinor<PREC>::template store<WD_NT_OUT>(fout, i, c);
@@ -696,8 +711,8 @@ bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger
 // parity, sit at their internal index >> 1.  Forward links come from the
 // parity-p half array gp, backward links U_mu(x - mu) from gq.  The hops are
 // summed in the order of the full stencil.
-// XR: the CG update x += alpha p, r -= alpha out_p in place of storing out
-// (the reduction is then |r|^2; with HASC and RED).  LF: the link form.
+// XR: the CG update r -= alpha out_p in place of storing out (the reduction
+// is then |r|^2; with HASC and RED).  LF: the link form.
 template <int PREC, bool DAG, bool RED, bool HASC, int GROUP, bool XR = false, int LF = PREC>
 __global__ void __launch_bounds__(256) k_hop_half(Geom g, const void *__restrict__ gp,
                                                   const void *__restrict__ gq, int p, FieldRef in,
@@ -805,15 +820,15 @@ static void launch_hop_half_xr_prec(const Geom &g, const void *gp, const void *g
                                     double k, double cs, int dagger, FieldRef in, FieldRef c,
                                     const XrArgs &xr, const RedArgs &red, Gate gate,
                                     hipStream_t s) {
-    const int nb = site_blocks(xr.x.V);
+    const int nb = site_blocks(xr.r.V);
     const dim3 grid(nb * in.nrhs);
     constexpr int G = HopGroup<PREC>::value;
     if (dagger)
         hipLaunchKernelGGL((k_hop_half<PREC, true, true, true, G, true, LF>), grid,
-                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.x, k, cs, red, gate, xr);
+                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.r, k, cs, red, gate, xr);
     else
         hipLaunchKernelGGL((k_hop_half<PREC, false, true, true, G, true, LF>), grid,
-                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.x, k, cs, red, gate, xr);
+                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.r, k, cs, red, gate, xr);
     launch_finalize(red, nb, gate.batch ? gate.mode : -1, s);
 }
 

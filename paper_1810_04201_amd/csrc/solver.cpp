@@ -207,13 +207,15 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     // are being timed; WD_GRAPH=0 turns it off.
     const char *ge = getenv("WD_GRAPH");
     use_graph_ = s_ != nullptr && !timing_enabled() && !(ge && atoi(ge) == 0);
-    // A^dag (A p) formed where x and r are updated (q never stored): 2 of
-    // the 9 field transfers of an iteration's vector updates saved.  The
+    // A^dag (A p) formed where r is updated (q never stored), and x += alpha p
+    // moved into the p update (p read once for both): besides the stencils'
+    // inputs an iteration moves 7 fields instead of 10.  The
     // marching stencil on the full lattice, the half-field stencil's second
     // launch on the even-odd form; WD_FUSE_XR=0 turns it off.
     const char *fx = getenv("WD_FUSE_XR");
     fuse_xr_ = !(fx && atoi(fx) == 0) &&
                (eo_ || dslash_xr_supported(lat_->g, prec_, nrhs, partials_cap_));
+    ctl_.lag_x = fuse_xr_ ? 1 : 0;
     return WD_OK;
 }
 
@@ -247,10 +249,10 @@ void Solve::op(bool first, const FieldRef &in, const FieldRef &out, const RedArg
 }
 
 // The second operator application of an iteration on in = A p, with the
-// x/r update fused into its last launch; false if nothing was launched
+// r update fused into its last launch; false if nothing was launched
 bool Solve::op_xr(const FieldRef &in, const RedArgs &rr, Gate gate) {
     const double k = p_.kappa;
-    const XrArgs xr{xl_, rl_, pl_};
+    const XrArgs xr{rl_};
     if (!eo_) return dslash_xr(lat_, gauge_lo_, k, d2_, in, xr, rr, gate, s_);
     hop_half(lat_, ghlo_, 1, k, 0.0, d2_, in, FieldRef{}, tmpl_, nullptr, gate, s_);
     hop_half_xr(lat_, ghlo_, 0, -k, 1.0, d2_, tmpl_, in, xr, rr, gate, s_);
@@ -306,11 +308,15 @@ void Solve::enqueue_inner(int iters) {
     RedArgs rr = red(RED_RR);
     for (int i = 0; i < iters; ++i) {
         op(true, pl_, tl_, &ra, g, true);
-        if (!fuse_xr_ || !op_xr(tl_, rr, g)) {
+        if (fuse_xr_) {
+            // r updated where A p is formed; x += alpha p with the p update
+            op_xr(tl_, rr, g);
+            launch_update_xp(xl_, pl_, rl_, g, s_);
+        } else {
             op(false, tl_, apl_, nullptr, g, true);
             launch_update_xr(xl_, rl_, pl_, apl_, rr, g, s_);
+            launch_update_p(pl_, rl_, g, s_);
         }
-        launch_update_p(pl_, rl_, g, s_);
         if ((i + 1) % rel_every_ == 0 || i + 1 == iters) enqueue_reliable();
     }
 }
@@ -352,7 +358,7 @@ void Solve::enqueue_reliable() {
     const Gate trig{st_, batch_, GATE_TRIGGER};
     const Gate rst{st_, batch_, GATE_RESTART};
     RedArgs rt = red(RED_TRUE);
-    launch_accum_zero(x64_, xl_, trig, s_);
+    launch_accum_zero(x64_, xl_, pl_, trig, s_);
     op(true, x64_, t64_, nullptr, trig, false);
     op(false, t64_, ax64_, nullptr, trig, false);
     launch_residual(r64_, bp_, ax64_, rt, trig, s_);
@@ -363,7 +369,7 @@ void Solve::enqueue_reliable() {
 void Solve::enqueue_finish() {
     const double k = p_.kappa;
     const Gate none{nullptr, nullptr, GATE_ACTIVE};
-    launch_accum_zero(x64_, xl_, Gate{st_, nullptr, GATE_ACTIVE}, s_);  // unconverged rhs
+    launch_accum_zero(x64_, xl_, pl_, Gate{st_, nullptr, GATE_ACTIVE}, s_);  // unconverged rhs
     RedArgs ra = red(RED_AUX);
     RedArgs ra2 = red(RED_AUX_ADD);
     RedArgs rb = red(RED_AUX2);

@@ -218,6 +218,8 @@ struct RhsState {
     int updates;     // reliable updates (true-residual recomputations)
     int restarted;   // the last reliable update restarted the recursion (until
                      // the next inner iteration): r_lo and p are to be reset
+    int pend;        // x lags one step (see SolveCtl::lag_x) and this rhs froze
+                     // with alpha p not yet in x_lo: the reliable update adds it
 };
 
 struct BatchState {
@@ -258,10 +260,11 @@ struct Gate {
 //   links:       U_t(x, -1), the links entering from the previous slab
 //                (float64 gauge tiles of V / Lt sites, mu = 3 planes)
 //   first, last: this slab holds global t = 0 / t = T - 1 (antiperiodic sign)
-// The CG update x += alpha p, r -= alpha q done by the stencil that forms
-// q = A p, so q is never stored (alpha from the rhs's state)
+// The CG residual update r -= alpha q done by the stencil that forms
+// q = A p, so q is never stored (alpha from the rhs's state); x += alpha p
+// then follows in the p update (launch_update_xp)
 struct XrArgs {
-    FieldRef x, r, p;
+    FieldRef r;
 };
 
 struct Halo {
@@ -278,6 +281,8 @@ struct SolveCtl {
     int max_inner;    // reliable update at least every max_inner iterations (0: never)
     int nrhs;
     int mixed;        // 1: inner iterations in low precision
+    int lag_x;        // 1: x += alpha p is done by the next p update (the
+                      // stencil that forms A p only updates r)
 };
 
 enum RedMode {
@@ -471,8 +476,8 @@ void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, doubl
                      double cs, int dagger, FieldRef in, FieldRef c, FieldRef out,
                      const RedArgs *red, Gate gate, hipStream_t s, bool r12 = false);
 // the same with c present and its output q consumed where it is formed:
-// x += alpha p, r -= alpha q (XrArgs on half fields), |r|^2 reduced with
-// red.mode and finalised; q is not stored
+// r -= alpha q (XrArgs on half fields), |r|^2 reduced with red.mode and
+// finalised; q is not stored
 void launch_hop_half_xr(const Geom &g, const void *gp, const void *gq, int p, double k,
                         double cs, int dagger, FieldRef in, FieldRef c, const XrArgs &xr,
                         const RedArgs &red, Gate gate, hipStream_t s, bool r12 = false);
@@ -493,7 +498,8 @@ void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagg
 
 // x64 += xlo ; xlo = 0: gate.mode GATE_TRIGGER for the rhs a reliable update
 // takes (with its batch test), otherwise every rhs that has not converged
-void launch_accum_zero(FieldRef x64, FieldRef xlo, Gate gate, hipStream_t s);
+// A pending alpha p (RhsState::pend) is added too: x64 += xlo + alpha p.
+void launch_accum_zero(FieldRef x64, FieldRef xlo, FieldRef p, Gate gate, hipStream_t s);
 
 // out = D in (dagger 0) or D^dag in (dagger 1); red != nullptr fuses the
 // reduction of |out|^2 with red->mode
@@ -502,9 +508,8 @@ void launch_accum_zero(FieldRef x64, FieldRef xlo, Gate gate, hipStream_t s);
 void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                    FieldRef out, const RedArgs *red, Gate gate, hipStream_t s,
                    const void *g12 = nullptr);
-// q = D in (or D^dag in) consumed where it is formed: x += alpha p,
-// r -= alpha q, |r|^2 reduced with red.mode (RED_RR) and finalised; q is not
-// stored.  Only the marching stencil does this: returns false (nothing
+// q = D in (or D^dag in) consumed where it is formed: r -= alpha q, |r|^2
+// reduced with red.mode (RED_RR) and finalised; q is not stored.  Only the marching stencil does this: returns false (nothing
 // launched) where it does not run
 bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                       const XrArgs &xr, const RedArgs &red, Gate gate, hipStream_t s,
@@ -516,6 +521,9 @@ void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const Red
                       Gate gate, hipStream_t s);
 // p = r + beta p for active rhs
 void launch_update_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s);
+// x += alpha p ; p = r + beta p (active rhs): the x update lagged behind the
+// r update of a stencil with XrArgs
+void launch_update_xp(FieldRef x, FieldRef p, FieldRef r, Gate gate, hipStream_t s);
 // r = b - Ax (Ax.data == nullptr: r = b) in float64, reduce |r|^2 with red.mode
 void launch_residual(FieldRef r, FieldRef b, FieldRef Ax, const RedArgs &red, Gate gate,
                      hipStream_t s);
