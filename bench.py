@@ -46,8 +46,6 @@ XR_BYTES_PER_SITE = {"f64": 576 + 192 + 2 * 192,
                      "f32": 192 + 96 + 2 * 96,
                      "f16": 96 + 52 + 2 * 96}
 FUSED_XR = os.environ.get("WD_FUSE_XR", "1") != "0"
-# the slab stencil reads float64 links as 18 reals
-HALO_BYTES_PER_SITE = 192 + 576 + 192
 
 
 def f64_bytes(lat):
@@ -378,7 +376,7 @@ def slab_share(np, torch, synth, wd):
     res = {"lattice": "48x48x48x12 (one of 8 t-slabs of 48x48x48x96)",
            "dslash_plain_ms": round(plain, 4), "halo_pack_ms": round(pack, 4),
            "dslash_halo_ms": round(halo, 4),
-           "dslash_halo_GBps_algorithmic": round(V * HALO_BYTES_PER_SITE / halo / 1e6, 1),
+           "dslash_halo_GBps_algorithmic": round(V * f64_bytes(lat)[0] / halo / 1e6, 1),
            "face_bytes_per_direction": face_bytes,
            "face_over_xgmi_link_us_estimate": round(face_bytes / 153e9 * 1e6, 1)}
     fa.close()

@@ -367,7 +367,7 @@ __device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
 // XR: the CG update that consumes q = A p is done where q is formed, so q is
 // never stored: r -= alpha q, and the reduction is |r|^2 (see XrArgs).  out
 // is unused.
-// LF: the link form (PREC's own, or F64-12 for float64; not with HALO).
+// LF: the link form (PREC's own, or F64-12 for float64).
 template <int PREC, bool DAG, bool RED, int GROUP, bool HALO = false, bool XR = false,
           int LF = PREC>
 __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *__restrict__ gauge,
@@ -434,11 +434,18 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
             h1[c] = scale(sg, h1[c]);
         }
         cx<R> u[9];
-        if constexpr (HALO)
+        if constexpr (HALO && LF == PREC) {
             Link<PREC>::load(prev_from_halo ? halo.links : gauge, 3,
                              prev_from_halo ? fbase + l : ip, u);
-        else
+        } else if constexpr (HALO) {
+            // the entering links are float64 with 18 reals
+            if (prev_from_halo)
+                Link<PREC>::load(halo.links, 3, fbase + l, u);
+            else
+                Link<LF>::load(gauge, 3, ip, u);
+        } else {
             Link<LF>::load(gauge, 3, ip, u);
+        }
         su3_mul<true>(u, h0, cw0);
         su3_mul<true>(u, h1, cw1);
     }
@@ -968,8 +975,9 @@ void launch_halo_links(const Geom &g, const double *canon, void *links, hipStrea
 
 bool halo_supported(const Geom &g) { return tm_eligible(g) && tm_fits<WD_F64>(g); }
 
-void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
-                        FieldRef out, const Halo &halo, hipStream_t s) {
+template <int LF>
+static void launch_halo_lf(const Geom &g, const void *gauge, double kappa, int dagger,
+                           FieldRef in, FieldRef out, const Halo &halo, hipStream_t s) {
     const int wvol = tm_wvol(g, WD_F64);
     const int nsub = g.bvol / wvol;
     const int tch = tm_chunk(g, in.nrhs * nsub);
@@ -979,16 +987,24 @@ void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagg
     constexpr int G = HopGroup<WD_F64>::value;
     const Gate none{nullptr, nullptr, GATE_ACTIVE};
     if (dagger) {
-        auto k = k_dslash_tm<WD_F64, true, false, G, true>;
+        auto k = k_dslash_tm<WD_F64, true, false, G, true, false, LF>;
         allow_lds(k, lds);
         hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, RedArgs{}, none, tch,
                            ncols, halo, XrArgs{});
     } else {
-        auto k = k_dslash_tm<WD_F64, false, false, G, true>;
+        auto k = k_dslash_tm<WD_F64, false, false, G, true, false, LF>;
         allow_lds(k, lds);
         hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, RedArgs{}, none, tch,
                            ncols, halo, XrArgs{});
     }
+}
+
+void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
+                        FieldRef out, const Halo &halo, hipStream_t s, const void *g12) {
+    if (g12)
+        launch_halo_lf<kLinkF64R12>(g, g12, kappa, dagger, in, out, halo, s);
+    else
+        launch_halo_lf<WD_F64>(g, gauge, kappa, dagger, in, out, halo, s);
 }
 
 }  // namespace wd

@@ -581,7 +581,8 @@ int wd_dslash_halo(wd_lattice *lat, double kappa, int dagger, const wd_field *in
                     (flags & WD_HALO_LAST) ? 1 : 0};
     const double k = -lat->hop_sign * kappa;
     timed("halo_f64", s, [&] {
-        launch_dslash_halo(lat->g, lat->gauge[WD_F64], k, dagger, in->ref, out->ref, halo, s);
+        launch_dslash_halo(lat->g, lat->gauge[WD_F64], k, dagger, in->ref, out->ref, halo, s,
+                           lat->gauge12);
     });
     (void)hipFreeAsync(mem, s);
     WD_LAUNCH_CHECK();

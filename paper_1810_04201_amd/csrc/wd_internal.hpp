@@ -494,7 +494,8 @@ void launch_halo_links(const Geom &g, const double *canon, void *links, hipStrea
 // the marching stencil with t hops across the slab ends from staged faces
 bool halo_supported(const Geom &g);
 void launch_dslash_halo(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
-                        FieldRef out, const Halo &halo, hipStream_t s);
+                        FieldRef out, const Halo &halo, hipStream_t s,
+                        const void *g12 = nullptr);
 
 // x64 += xlo ; xlo = 0: gate.mode GATE_TRIGGER for the rhs a reliable update
 // takes (with its batch test), otherwise every rhs that has not converged

@@ -81,6 +81,11 @@ def test_lattice_lifecycle_host_only():
     v = ctypes.c_int64()
     assert wd.lib.wd_lattice_volume(lat.handle, ctypes.byref(v)) == 0 and v.value == 1920
     assert lat.gauge_bytes() == 0
+    # no gauge yet: 18-real float64 links, deviation unchecked
+    assert lat.links_info() == (18, -1.0)
+    n = ctypes.c_int(7)
+    assert wd.lib.wd_lattice_links_info(lat.handle, ctypes.byref(n), None) == 0 and n.value == 18
+    assert wd.lib.wd_lattice_links_info(None, None, None) == wd.WD_ERR_ARG
     lat.close()
 
 
