@@ -740,7 +740,9 @@ def probe(np, torch, synth, wd):
             lat.apply_schur(0.1245, psi, out, prec=prec)
         torch.cuda.synchronize()
         print(f"probe schur {prec} done", flush=True)
-    # CG iterations (the stencil with the fused x/r update), FP64 and mixed
+    # CG iterations (the stencil with the fused r update), FP64 and mixed;
+    # eager launches (no graph replay) for the counters
+    os.environ["WD_GRAPH"] = "0"
     x = torch.zeros_like(psi)
     for prec in ("f64", "f16"):
         x.zero_()
@@ -766,8 +768,12 @@ def pmc_summary(args):
     fetch = _pmc_rows(args.pmc_summary[0])
     write = _pmc_rows(args.pmc_summary[1])
     copy_bytes = 256 * 1024 * 1024 * 8
+    # the 2 GiB calibration copies: the largest copy dispatches (small copies
+    # of status words run too)
     cf = [r for r in fetch if "copyBuffer" in r["name"]]
     cw = [r for r in write if "copyBuffer" in r["name"]]
+    cf = [r for r in cf if r["grid"] == max(q["grid"] for q in cf)]
+    cw = [r for r in cw if r["grid"] == max(q["grid"] for q in cw)]
     ff = copy_bytes / (statistics.median(r["FETCH_SIZE"] for r in cf) * 1024)
     wf = copy_bytes / (statistics.median(r["WRITE_SIZE"] for r in cw) * 1024)
     V = 48 * 48 * 48 * 96
@@ -820,7 +826,10 @@ def pmc_summary(args):
         fk = statistics.mean(r["FETCH_SIZE"] for r in fr)
         wk = statistics.mean(r["WRITE_SIZE"] for r in wr)
         traffic = fk * 1024 * ff + wk * 1024 * wf
-        per_site = 8 * LINK_BYTES[prec] // 4 + 2.5 * SPINOR_BYTES[prec]
+        # the last template argument is the link form (3: float64, 12 reals)
+        link = 384 if prec == "f64" and fr[0]["name"].split(">")[0].endswith(", 3") else \
+            LINK_BYTES[prec]
+        per_site = 2 * link + 2.5 * SPINOR_BYTES[prec]
         alg = V // 2 * per_site
         out["kernels"][f"hop_half_{prec}"] = {
             "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk, "traffic_bytes": round(traffic),
