@@ -323,13 +323,15 @@ constexpr int kSiteBlock = 256;
 
 inline int site_blocks(int V) { return blocks_for(V, kSiteBlock); }
 
-// largest brick (workgroup) of the time-marching stencil
+// largest workgroup (part of a brick slice) of the time-marching stencil
 #ifndef WD_TM_MAXB
 #define WD_TM_MAXB 512
 #endif
 constexpr int kTmMaxBlock = WD_TM_MAXB;
 
-inline bool tm_eligible(const Geom &g) { return g.bvol % 64 == 0 && g.bvol <= kTmMaxBlock; }
+// any brick of whole tiles: a workgroup takes a part of at most kTmMaxBlock
+// sites (tm_wvol)
+inline bool tm_eligible(const Geom &g) { return g.bvol % 64 == 0; }
 
 // sites per marching workgroup: a contiguous part of a brick slice (a
 // multiple of 64 dividing bvol).  float64 takes up to 384 (one workgroup per CU holds its
