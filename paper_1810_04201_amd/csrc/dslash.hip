@@ -790,36 +790,237 @@ __global__ void __launch_bounds__(256) k_hop_half(Geom g, const void *__restrict
     if (RED) reduce_block(nrm, red.partials, (size_t)sb * nrhs + rhs);
 }
 
-template <int PREC, bool DAG, bool RED, bool HASC, int LF = PREC>
-static void launch_hop_half_k(dim3 grid, hipStream_t s, const Geom &g, const void *gp,
-                              const void *gq, int p, FieldRef in, FieldRef c, FieldRef out,
-                              double k, double cs, const RedArgs &r, Gate gate) {
+// The half-field stencil in the time-marching form (lattices whose brick
+// slices hold a multiple of 64 sites of each parity).  The parity-p half of
+// a brick slice is bvol / 2 consecutive entries of a half field, and so is
+// the parity-(1-p) half, pair by pair: output entry hs + l and input entry
+// hs + l sit on the same site pair.  One workgroup per (chunk, column, part,
+// rhs) marches t as the full stencil does, with two LDS images of its part
+// of the input half slice:
+//  - x/y/z neighbours (input entries nbr >> 1) from the current image when
+//    they fall in the part, else from memory;
+//  - the forward t neighbour of output lane l is input entry l of the next
+//    half slice (same x, y, z; the other parity), from the new image;
+//  - the backward t hop of slice t+1 is input entry l of slice t with its own
+//    U_t (parity 1 - p links), carried in registers.
+// Hops are summed in the order of k_hop_half.  Forward links come from gp at
+// the output entry, backward ones from gq at the neighbour's entry.
+template <int PREC, bool DAG, bool RED, bool HASC, int GROUP, bool XR, int LF>
+__global__ void __launch_bounds__(kTmMaxBlock) k_hop_half_tm(Geom g, const void *__restrict__ gp,
+                                                     const void *__restrict__ gq, int p,
+                                                     FieldRef in, FieldRef c, FieldRef out,
+                                                     double k_d, double cs_d, RedArgs red,
+                                                     Gate gate, int tchunk, int ncols,
+                                                     XrArgs xr) {
+    using R = typename Spinor<PREC>::R;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ double wsum[kTmMaxBlock / 64];
+    if (gate_off(gate)) return;  // grid-uniform
+    const int nrhs = in.nrhs;
+    const int wvol = (int)blockDim.x;  // entries of this workgroup's part
+    const int hvol = g.bvol >> 1;      // entries of one parity per brick slice
+    const int nsub = hvol / wvol;
+    const int lb = logical_block();
+    const int cb = lb / nrhs;
+    const int rhs = lb - cb * nrhs;
+    if (!gate_rhs(gate, rhs)) return;  // workgroup-uniform
+    const FieldRef fin = rhs_view(in, rhs);
+    const int cc = cb / nsub;
+    const int hp = cb - cc * nsub;
+    const int chunk = cc / ncols;
+    const int col = cc - chunk * ncols;
+    const int Lt = g.L[3];
+    const int l = (int)threadIdx.x;
+    const int t0 = chunk * tchunk;
+    const int t1 = t0 + tchunk < Lt ? t0 + tchunk : Lt;
+    // first entry of this workgroup's part of half slice t: hbase + t * hvol
+    const int hbase = col * Lt * hvol + hp * wvol;
+    char *img0 = lds;
+    char *img1 = lds + slice_bytes<PREC>(wvol);
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const R kappa = (R)k_d;
+
+    // prologue: input half slice t0 into image 0, and the backward t hop of
+    // slice t0 from input entry l of slice t0 - 1
+    slice_copy<PREC>(fin, (hbase + t0 * hvol) >> 6, img0);
+    cx<R> cw0[3], cw1[3];
+    {
+        const int ip = hbase + (t0 == 0 ? Lt - 1 : t0 - 1) * hvol + l;
+        cx<R> v[12];
+        Spinor<PREC>::load(fin, ip, v);
+        cx<R> h0[3], h1[3];
+        project<3, SB>(v, h0, h1);
+        const R sg = (g.antiperiodic && t0 == 0) ? R(-1) : R(1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            h0[k] = scale(sg, h0[k]);
+            h1[k] = scale(sg, h1[k]);
+        }
+        cx<R> u[9];
+        Link<LF>::load(gq, 3, ip, u);
+        su3_mul<true>(u, h0, cw0);
+        su3_mul<true>(u, h1, cw1);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int t = t0; t < t1; ++t) {
+        const bool odd = (t - t0) & 1;
+        const FieldRef cur = lds_view(fin, odd ? img1 : img0);
+        const FieldRef nxt = lds_view(fin, odd ? img0 : img1);
+        const int tn = t + 1 < Lt ? t + 1 : 0;
+        slice_copy<PREC>(fin, (hbase + tn * hvol) >> 6, (char *)nxt.data);
+        const int hs = hbase + t * hvol;
+        const int H = hs + l;  // output entry
+        // (not with 18-real float64 links: registers would spill)
+        constexpr bool XPRE = XR && ((WD_XR_PREFETCH >> PREC) & 1) && LF != WD_F64;
+        cx<R> rpre[XPRE ? 12 : 1];
+        if constexpr (XPRE)
+            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::load(rhs_view(xr.r, rhs), H, rpre);
+        const Nbrs nb = neighbours(g, site_of_half(g, H, p));
+        cx<R> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+#define WD_HOP_FENCE(k) \
+    if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
+        hop_s<0, SF, false, PREC, LF>(gp, fin, cur, hs, wvol, nb.xp >> 1, H, acc);
+        WD_HOP_FENCE(1);
+        hop_s<0, SB, true, PREC, LF>(gq, fin, cur, hs, wvol, nb.xm >> 1, nb.xm >> 1, acc);
+        WD_HOP_FENCE(2);
+        hop_s<1, SF, false, PREC, LF>(gp, fin, cur, hs, wvol, nb.yp >> 1, H, acc);
+        WD_HOP_FENCE(3);
+        hop_s<1, SB, true, PREC, LF>(gq, fin, cur, hs, wvol, nb.ym >> 1, nb.ym >> 1, acc);
+        WD_HOP_FENCE(4);
+        hop_s<2, SF, false, PREC, LF>(gp, fin, cur, hs, wvol, nb.zp >> 1, H, acc);
+        WD_HOP_FENCE(5);
+        hop_s<2, SB, true, PREC, LF>(gq, fin, cur, hs, wvol, nb.zm >> 1, nb.zm >> 1, acc);
+        WD_HOP_FENCE(6);
+#undef WD_HOP_FENCE
+        cx<R> ut[9], ub[9];
+        Link<LF>::template load<WD_NT_LINK || WD_NT_LINK_T>(gp, 3, H, ut);
+        Link<LF>::template load<WD_NT_LINK || WD_NT_LINK_T>(gq, 3, H, ub);
+        // the next half slice has landed in LDS (every wave's copy)
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        {
+            cx<R> nx[12];
+            Spinor<PREC>::load(nxt, l, nx);
+            hop_p<3, SF, false>(nx, ut, g.antiperiodic && t == Lt - 1, acc);
+        }
+        accumulate<3, SB>(cw0, cw1, acc);
+        // carry for slice t + 1: input entry l of this slice with its U_t
+        {
+            cx<R> v[12];
+            Spinor<PREC>::load(cur, l, v);
+            cx<R> h0[3], h1[3];
+            project<3, SB>(v, h0, h1);
+            su3_mul<true>(ub, h0, cw0);
+            su3_mul<true>(ub, h1, cw1);
+        }
+        cx<R> o[12];
+        if constexpr (HASC) {
+            Spinor<PREC>::load(rhs_view(c, rhs), H, o);
+            const R cs = (R)cs_d;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) o[k] = scale(cs, o[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) o[k] = {R(0), R(0)};
+        }
+        double nrm = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            o[k] = o[k] - scale(kappa, acc[k]);
+            if (RED && !XR)
+                nrm += (double)o[k].re * (double)o[k].re + (double)o[k].im * (double)o[k].im;
+        }
+        if constexpr (XPRE)
+            nrm = xr_site_r<PREC>(xr, rhs, H, (R)gate.st[rhs].alpha, o, rpre);
+        else if constexpr (XR)
+            nrm = xr_site<PREC>(xr, rhs, H, (R)gate.st[rhs].alpha, o);
+        else
+            Spinor<PREC>::template store<WD_NT_OUT>(rhs_view(out, rhs), H, o);
+        if (RED) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+            if ((l & 63) == 0) wsum[l >> 6] = nrm;
+        }
+        __syncthreads();  // the current image is free for the next copy
+        if (RED && l == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < (wvol >> 6); ++w) sum += wsum[w];
+            red.partials[(((size_t)col * Lt + t) * nsub + hp) * nrhs + rhs] = sum;
+        }
+    }
+}
+
+// WD_EO_SITE=1 keeps the half-field stencil one lane per site (tuning and
+// tests; read at every launch)
+static bool eo_site_forced() {
+    const char *e = getenv("WD_EO_SITE");
+    return e && atoi(e) != 0;
+}
+
+// The marching form pays where link and spinor bytes bound the launch: at
+// 48^3 x 96 float64 half launches take 1.29-1.49 ms against 1.65-1.77 one
+// lane per site, float32 -2%, while binary16 (bound by its arithmetic) is
+// 3-8% slower marching and stays one lane per site.
+template <int PREC>
+static bool eo_tm_ok(const Geom &g, int nrhs, bool red, int64_t partials_cap) {
+    static const size_t cap = max_lds_per_block();
+    const int w = eo_wvol(g, PREC);
+    return PREC != WD_F16 && w > 0 && !eo_site_forced() && !g_force_site_kernel &&
+           2 * slice_bytes<PREC>(w) + 64 <= cap &&
+           (!red || (int64_t)(g.V / 2 / w) * nrhs <= partials_cap);
+}
+
+// one half-field launch, marching where the geometry allows, with its
+// finaliser
+template <int PREC, bool DAG, bool RED, bool HASC, bool XR, int LF>
+static void launch_eo(const Geom &g, const void *gp, const void *gq, int p, FieldRef in,
+                      FieldRef c, FieldRef out, double k, double cs, const RedArgs &r,
+                      Gate gate, const XrArgs &xr, hipStream_t s) {
     constexpr int G = HopGroup<PREC>::value;
-    hipLaunchKernelGGL((k_hop_half<PREC, DAG, RED, HASC, G, false, LF>), grid, dim3(kSiteBlock),
-                       0, s, g, gp, gq, p, in, c, out, k, cs, r, gate, XrArgs{});
+    int nb;
+    if (eo_tm_ok<PREC>(g, in.nrhs, RED, r.partials_cap)) {
+        const int w = eo_wvol(g, PREC);
+        const int nsub = g.bvol / 2 / w;
+        const int tch = tm_chunk(g, in.nrhs * nsub);
+        const int ncols = g.V / (g.L[3] * g.bvol);
+        const dim3 grid(tm_blocks(g, tch) * nsub * in.nrhs), bs(w);
+        const size_t lds = 2 * slice_bytes<PREC>(w);
+        auto kern = k_hop_half_tm<PREC, DAG, RED, HASC, G, XR, LF>;
+        allow_lds(kern, lds);
+        hipLaunchKernelGGL(kern, grid, bs, lds, s, g, gp, gq, p, in, c, out, k, cs, r, gate, tch,
+                           ncols, xr);
+        nb = g.V / 2 / w;
+    } else {
+        nb = site_blocks(out.V);
+        hipLaunchKernelGGL((k_hop_half<PREC, DAG, RED, HASC, G, XR, LF>), dim3(nb * in.nrhs),
+                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, out, k, cs, r, gate, xr);
+    }
+    if (RED) launch_finalize(r, nb, gate.batch ? gate.mode : -1, s);
 }
 
 template <int PREC, int LF = PREC>
 static void launch_hop_half_prec(const Geom &g, const void *gp, const void *gq, int p, double k,
                                  double cs, int dagger, FieldRef in, FieldRef c, FieldRef out,
                                  const RedArgs *red, Gate gate, hipStream_t s) {
-    const int nb = site_blocks(out.V);
-    const dim3 grid(nb * in.nrhs);
     RedArgs r{};
     if (red) r = *red;
+    const XrArgs nx{};
     const bool hc = c.data != nullptr;
     const int sel = (dagger ? 4 : 0) | (red ? 2 : 0) | (hc ? 1 : 0);
     switch (sel) {
-        case 0: launch_hop_half_k<PREC, false, false, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 1: launch_hop_half_k<PREC, false, false, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 2: launch_hop_half_k<PREC, false, true, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 3: launch_hop_half_k<PREC, false, true, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 4: launch_hop_half_k<PREC, true, false, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 5: launch_hop_half_k<PREC, true, false, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        case 6: launch_hop_half_k<PREC, true, true, false, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
-        default: launch_hop_half_k<PREC, true, true, true, LF>(grid, s, g, gp, gq, p, in, c, out, k, cs, r, gate); break;
+        case 0: launch_eo<PREC, false, false, false, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
+        case 1: launch_eo<PREC, false, false, true, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
+        case 2: launch_eo<PREC, false, true, false, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
+        case 3: launch_eo<PREC, false, true, true, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
+        case 4: launch_eo<PREC, true, false, false, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
+        case 5: launch_eo<PREC, true, false, true, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
+        case 6: launch_eo<PREC, true, true, false, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
+        default: launch_eo<PREC, true, true, true, false, LF>(g, gp, gq, p, in, c, out, k, cs, r, gate, nx, s); break;
     }
-    if (red) launch_finalize(r, nb, gate.batch ? gate.mode : -1, s);
 }
 
 template <int PREC, int LF = PREC>
@@ -827,16 +1028,11 @@ static void launch_hop_half_xr_prec(const Geom &g, const void *gp, const void *g
                                     double k, double cs, int dagger, FieldRef in, FieldRef c,
                                     const XrArgs &xr, const RedArgs &red, Gate gate,
                                     hipStream_t s) {
-    const int nb = site_blocks(xr.r.V);
-    const dim3 grid(nb * in.nrhs);
-    constexpr int G = HopGroup<PREC>::value;
+    // out only sizes the launch (xr.r is a half field like it)
     if (dagger)
-        hipLaunchKernelGGL((k_hop_half<PREC, true, true, true, G, true, LF>), grid,
-                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.r, k, cs, red, gate, xr);
+        launch_eo<PREC, true, true, true, true, LF>(g, gp, gq, p, in, c, xr.r, k, cs, red, gate, xr, s);
     else
-        hipLaunchKernelGGL((k_hop_half<PREC, false, true, true, G, true, LF>), grid,
-                           dim3(kSiteBlock), 0, s, g, gp, gq, p, in, c, xr.r, k, cs, red, gate, xr);
-    launch_finalize(red, nb, gate.batch ? gate.mode : -1, s);
+        launch_eo<PREC, false, true, true, true, LF>(g, gp, gq, p, in, c, xr.r, k, cs, red, gate, xr, s);
 }
 
 void launch_hop_half_xr(const Geom &g, const void *gp, const void *gq, int p, double k, double cs,

@@ -346,6 +346,17 @@ inline int tm_wvol(const Geom &g, int prec) {
     return g.bvol;
 }
 
+// entries per workgroup of the marching half-field stencil: the largest
+// multiple of 64 within the full stencil's cap that divides a half slice
+// (bvol / 2 entries of one parity); 0 where a half slice is not whole tiles
+inline int eo_wvol(const Geom &g, int prec) {
+    const int hvol = g.bvol / 2;
+    const int cap = prec == WD_F64 ? 384 : 256;
+    for (int w = cap; w >= 64; w -= 64)
+        if (hvol % w == 0) return w;
+    return 0;
+}
+
 // time slices per chunk: enough workgroups over all rhs to fill the chip (a
 // multiple of 8 chunks where the extent allows); env_chunk > 0 overrides
 // (tuning)

@@ -49,6 +49,52 @@ static int check(int Lx, int Ly, int Lz, int Lt) {
                         wd::coords_of(g, i, x, y, z, t);
                         if ((i >> 1) != h || ((x + y + z + t) & 1) != p) ++fails;
                     }
+            // the marching half-field stencil's entries: each output entry of
+            // either parity once, its t neighbours where the images hold
+            // them, and the partials within the capacity
+            if (wd::eo_supported(g))
+                for (int prec = 0; prec < 3; ++prec) {
+                    const int w = wd::eo_wvol(g, prec);
+                    if (!w) continue;
+                    const int hvol = g.bvol / 2, nsub = hvol / w;
+                    const int ncols = g.V / (Lt * g.bvol);
+                    if (hvol % w || w % 64 || w > wd::kTmMaxBlock) ++fails;
+                    if ((long long)(g.V / 2 / w) > wd::reduce_partials_cap(g, 1)) ++fails;
+                    for (int ch : {1, 3, Lt}) {
+                        const int nch = (Lt + ch - 1) / ch;
+                        for (int p = 0; p < 2; ++p) {
+                            std::vector<int> out(g.V / 2, 0);
+                            for (int cb = 0; cb < ncols * nch * nsub; ++cb) {
+                                const int cc = cb / nsub, hp = cb % nsub;
+                                const int chunk = cc / ncols, col = cc % ncols;
+                                const int t0 = chunk * ch, t1 = t0 + ch < Lt ? t0 + ch : Lt;
+                                const int hbase = col * Lt * hvol + hp * w;
+                                if (hbase % 64) ++fails;
+                                for (int l = 0; l < w; ++l) {
+                                    const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+                                    const int i0 = wd::site_of_half(g, hbase + t0 * hvol + l, p);
+                                    if ((wd::neighbours(g, i0).tm >> 1) != hbase + tp * hvol + l) ++fails;
+                                    for (int t = t0; t < t1; ++t) {
+                                        const int H = hbase + t * hvol + l;
+                                        if (H < 0 || H >= g.V / 2) { ++fails; continue; }
+                                        out[H]++;
+                                        const int i = wd::site_of_half(g, H, p);
+                                        const wd::Nbrs n = wd::neighbours(g, i);
+                                        const int tn = t + 1 < Lt ? t + 1 : 0;
+                                        if ((n.tp >> 1) != hbase + tn * hvol + l) ++fails;
+                                        if (wd::site_of_half(g, n.tp >> 1, 1 - p) != n.tp) ++fails;
+                                        if (t + 1 < t1) {
+                                            const int i1 = wd::site_of_half(g, H + hvol, p);
+                                            if ((wd::neighbours(g, i1).tm >> 1) != H) ++fails;
+                                        }
+                                    }
+                                }
+                            }
+                            for (int h = 0; h < g.V / 2; ++h)
+                                if (out[h] != 1) ++fails;
+                        }
+                    }
+                }
             // reduction partials: room for every reducing launch shape (a
             // launch writes index block * nrhs + rhs for each of its blocks
             // per rhs)
@@ -116,6 +162,8 @@ int main() {
     f += check(24, 6, 8, 4);
     f += check(12, 12, 12, 12);
     f += check(16, 16, 16, 8);
+    f += check(16, 8, 8, 4);
+    f += check(8, 8, 12, 6);
     printf(f ? "FAIL\n" : "OK\n");
     return f ? 1 : 0;
 }

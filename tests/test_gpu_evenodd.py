@@ -276,3 +276,29 @@ def test_schur_after_gauge_form_changes(env):
     # F64-18 + F64-12 + 12-real halves; F64-18 + 18-real halves
     assert bytes_seen[0] == bytes_seen[2] == V * 576 + V * 384 + V * 384
     assert bytes_seen[1] == V * 576 + V * 576
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("dims,brick", [((8, 8, 8, 8), None), ((8, 8, 12, 6), "8,8,6"),
+                                        ((16, 8, 8, 4), "16,8,2")])
+def test_marching_half_stencil_equals_site_form(env, monkeypatch, prec, dims, brick):
+    """The marching half-field stencil (half slices of 64-multiples staged in
+    LDS; float64 and float32) against the one-lane-per-site form
+    (WD_EO_SITE=1): the same hops in the same order, so M and M^dag agree to
+    the last bits, with 3 rhs."""
+    torch, dev, wd = env
+    if brick:
+        monkeypatch.setenv("WD_BRICK", brick)
+    U = gauge(dims, 161)
+    psi = synth.gaussian_sources(dims, [162, 163, 164])
+    res = {}
+    for site in ("0", "1"):
+        monkeypatch.setenv("WD_EO_SITE", site)
+        for dagger in (0, 1):
+            res[site, dagger] = _schur(env, dims, U, psi, 0.1245, prec, dagger, nrhs=3)
+    ev = evenodd.parity(dims) == 0
+    for dagger in (0, 1):
+        a, b = res["0", dagger], res["1", dagger]
+        assert site_rel_err(a[:, ev], b[:, ev]) <= {"f64": 1e-15, "f32": 1e-6}[prec]
+        for k in range(3):
+            _check_schur(a[k], U, psi[k], dims, 0.1245, prec, dagger)
