@@ -818,9 +818,13 @@ def pmc_summary(args):
     # even-odd half-field stencil (k_hop_half): a launch writes V/2 sites,
     # reads every link once and the other half's spinors, and (every second
     # launch of M) a c field
-    for prec, tag in (("f64", "k_hop_half<0"), ("f16", "k_hop_half<2")):
-        fr = [r for r in fetch if tag in r["name"]]
-        wr = [r for r in write if tag in r["name"]]
+    for prec, i in (("f64", 0), ("f16", 2)):
+        # the marching form where the probe ran it, else one lane per site
+        for tag in (f"k_hop_half_tm<{i}", f"k_hop_half<{i}"):
+            fr = [r for r in fetch if tag in r["name"]]
+            wr = [r for r in write if tag in r["name"]]
+            if fr and wr:
+                break
         if not fr or not wr:
             continue
         fk = statistics.mean(r["FETCH_SIZE"] for r in fr)
@@ -832,6 +836,7 @@ def pmc_summary(args):
         per_site = 2 * link + 2.5 * SPINOR_BYTES[prec]
         alg = V // 2 * per_site
         out["kernels"][f"hop_half_{prec}"] = {
+            "kernel": tag.split("<")[0],
             "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk, "traffic_bytes": round(traffic),
             "algorithmic_bytes": alg, "traffic_over_algorithmic": round(traffic / alg, 3),
             "traffic_bytes_per_output_site": round(traffic / (V // 2), 1)}

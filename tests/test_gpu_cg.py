@@ -331,3 +331,27 @@ def test_fused_update_equals_separate_update(env, monkeypatch, prec, nrhs):
             assert rel(xf[k], xu[k]) <= 1e-9
     assert rel(xf[0], xo) <= max(1e-9, 2e-10 * cond)
     assert rel(xu[0], xo) <= max(1e-9, 2e-10 * cond)
+
+
+@pytest.mark.parametrize("fuse", ["1", "0"])
+@pytest.mark.parametrize("dims,n", [((4, 6, 8, 10), 20), ((8, 8, 8, 8), 7), ((2, 4, 2, 6), 11)])
+def test_fp64_iterate_after_max_iter_equals_oracle_iterate(env, monkeypatch, fuse, dims, n):
+    """A solve stopped by max_iter returns the n-th CG iterate: with the fused
+    iteration the last alpha p is still pending when the rhs freezes, and the
+    final reliable update adds it.  Checked against the oracle's iterate
+    after exactly n steps, on the marching and the one-lane-per-site
+    stencils."""
+    torch, dev, wd = env
+    monkeypatch.setenv("WD_FUSE_XR", fuse)
+    U = gauge(dims, 171)
+    b = synth.gaussian_spinor(dims, 172)
+    rc, info, x = _solve(env, dims, U, b, 0.124, tol=1e-14, max_iter=n)
+    assert rc == wd.WD_ERR_NOCONV and info[0]["iters"] == n
+    xo, it, _ = _oracle_n(dims, U, b, 0.124, n)
+    assert it == n
+    assert rel(x, xo) <= 1e-11
+
+
+def _oracle_n(dims, U, b, kappa, n):
+    return cg.cgnr(lambda v: wilson.apply_D(U, v, dims, kappa),
+                   lambda v: wilson.apply_Ddag(U, v, dims, kappa), b, tol=1e-30, max_iter=n)
