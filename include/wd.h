@@ -110,10 +110,11 @@ int wd_lattice_volume(const wd_lattice *lat, int64_t *volume);
  * float64 18-real form now (the low-precision 12-real forms are derived
  * from it on first use).  It also measures how far each link is from
  * special unitary (the largest |row 2 - conj(row 0 x row 1)|, Sec. 6.1's
- * compressed form); if no link is further than 1e-14, the float64 links are
- * kept as 12 reals too, and every float64 stencil on the full lattice reads
- * that form (384 instead of 576 link bytes per site; the rebuilt row agrees
- * to rounding).  Environment WD_LINKS64_12=0 skips the check and the form.
+ * compressed form); if no link is further than 1e-14 (and the device has
+ * room for it), the float64 links are kept as 12 reals too, and the float64
+ * marching stencils read that form (384 instead of 576 link bytes per site;
+ * the rebuilt row agrees to rounding).  Environment WD_LINKS64_12=0 skips
+ * the check and the form.
  * The library keeps its own copy; U may be freed after the stream reaches
  * this point.  Synchronises `stream`. */
 int wd_set_gauge(wd_lattice *lat, const double *U, void *stream);

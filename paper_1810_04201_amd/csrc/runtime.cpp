@@ -339,15 +339,15 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
         memcpy(&dev, &hm, sizeof(dev));
         lat->su3_dev = dev;
     }
-    if (want12 && lat->su3_dev <= kSu3Tol) {
-        if (!lat->gauge12) {
-            void *p = nullptr;
-            hipError_t he = hipMalloc(&p, gauge_bytes(kLinkF64R12, lat->g.V));
-            if (he != hipSuccess)
-                return fail(WD_ERR_NOMEM, "hipMalloc of the F64-12 gauge form failed: %s",
-                            hipGetErrorString(he));
+    if (want12 && lat->su3_dev <= kSu3Tol && !lat->gauge12) {
+        // without memory for it the lattice keeps 18 reals only
+        void *p = nullptr;
+        if (hipMalloc(&p, gauge_bytes(kLinkF64R12, lat->g.V)) == hipSuccess)
             lat->gauge12 = p;
-        }
+        else
+            (void)hipGetLastError();
+    }
+    if (want12 && lat->su3_dev <= kSu3Tol && lat->gauge12) {
         launch_gauge_lo(lat->gauge[WD_F64], lat->gauge12, kLinkF64R12, lat->g.V, s);
     } else if (lat->gauge12) {
         (void)hipFree(lat->gauge12);

@@ -209,8 +209,8 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     use_graph_ = s_ != nullptr && !timing_enabled() && !(ge && atoi(ge) == 0);
     // A^dag (A p) formed where r is updated (q never stored), and x += alpha p
     // moved into the p update (p read once for both): besides the stencils'
-    // inputs an iteration moves 7 fields instead of 10.  The
-    // marching stencil on the full lattice, the half-field stencil's second
+    // inputs an iteration moves 7 fields instead of 10.  Done by the
+    // marching stencil on the full lattice and by the second half-field
     // launch on the even-odd form; WD_FUSE_XR=0 turns it off.
     const char *fx = getenv("WD_FUSE_XR");
     fuse_xr_ = !(fx && atoi(fx) == 0) &&
