@@ -442,6 +442,12 @@ __global__ void k_update_p(FieldRef p, FieldRef r, Gate gate) {
     Spinor<PPP>::store(pf, i, o);
 }
 
+// non-temporal loads and stores in k_update_xp: each field streams through
+// once per iteration (48^3 x 96: -5% float64, -8% in the binary16 mode)
+#ifndef WD_NT_XP
+#define WD_NT_XP 1
+#endif
+
 // x += alpha p ; p = r + beta p: the x update of the iteration whose r
 // update a stencil did, merged with the p update (p read once).  Same
 // arithmetic as k_update_xr's x update and k_update_p.
@@ -459,18 +465,18 @@ __global__ void k_update_xp(FieldRef x, FieldRef p, FieldRef r, Gate gate) {
     const R alpha = (R)st.alpha, beta = (R)st.beta;
     cx<RP> q[12];
     cx<R> v[12];
-    Spinor<PPP>::load(pf, i, q);
-    Spinor<PX>::load(xf, i, v);
+    Spinor<PPP>::template load<WD_NT_XP>(pf, i, q);
+    Spinor<PX>::template load<WD_NT_XP>(xf, i, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k)
         v[k] = {v[k].re + alpha * (R)q[k].re, v[k].im + alpha * (R)q[k].im};
-    Spinor<PX>::store(xf, i, v);
-    Spinor<PX>::load(rhs_view(r, rhs), i, v);
+    Spinor<PX>::template store<WD_NT_XP>(xf, i, v);
+    Spinor<PX>::template load<WD_NT_XP>(rhs_view(r, rhs), i, v);
     cx<RP> o[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k)
         o[k] = {(RP)(v[k].re + beta * (R)q[k].re), (RP)(v[k].im + beta * (R)q[k].im)};
-    Spinor<PPP>::store(pf, i, o);
+    Spinor<PPP>::template store<WD_NT_XP>(pf, i, o);
 }
 
 void launch_update_xp(FieldRef x, FieldRef p, FieldRef r, Gate gate, hipStream_t s) {

@@ -90,10 +90,11 @@ template <>
 struct Spinor<WD_F64> {
     using R = double;
     static constexpr size_t kTileBytes = 12 * 1024;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            double2 d = *(const double2 *)tile_elem(f.data, kTileBytes, i, k);
+            const d2_t d = ldv<NT>((const d2_t *)tile_elem(f.data, kTileBytes, i, k));
             v[k] = {d.x, d.y};
         }
     }
@@ -109,10 +110,11 @@ template <>
 struct Spinor<WD_F32> {
     using R = float;
     static constexpr size_t kTileBytes = 6 * 1024;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            float4 q = *(const float4 *)tile_elem(f.data, kTileBytes, i, j);
+            const f4_t q = ldv<NT>((const f4_t *)tile_elem(f.data, kTileBytes, i, j));
             v[2 * j] = {q.x, q.y};
             v[2 * j + 1] = {q.z, q.w};
         }
@@ -134,11 +136,12 @@ struct Spinor<WD_F16> {
         return (const float *)((const char *)f.data + (size_t)(i >> 6) * kTileBytes + 3 * 1024 +
                                (i & 63) * 4);
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const FieldRef &f, int i, cx<R> v[12]) {
-        const float s = *scale_ptr(f, i);
+        const float s = ldv<NT>(scale_ptr(f, i));
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            h8_t q = *(const h8_t *)tile_elem(f.data, kTileBytes, i, j);
+            const h8_t q = ldv<NT>((const h8_t *)tile_elem(f.data, kTileBytes, i, j));
 #pragma unroll
             for (int m = 0; m < 4; ++m)
                 v[4 * j + m] = {s * (float)q[2 * m], s * (float)q[2 * m + 1]};

@@ -52,6 +52,10 @@
 #ifndef WD_XR_PREFETCH
 #define WD_XR_PREFETCH 1
 #endif
+// the prefetched r loaded non-temporally: read once per iteration (-1%)
+#ifndef WD_NT_RLOAD
+#define WD_NT_RLOAD 1
+#endif
 
 namespace wd {
 
@@ -465,7 +469,8 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
         constexpr bool XPRE = XR && ((WD_XR_PREFETCH >> PREC) & 1);
         cx<R> rpre[XPRE ? 12 : 1];
         if constexpr (XPRE)
-            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::load(rhs_view(xr.r, rhs), i, rpre);
+            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::template load<WD_NT_RLOAD>(
+                rhs_view(xr.r, rhs), i, rpre);
         const Nbrs nb = neighbours(g, i);
         cx<R> acc[12];
 #pragma unroll
@@ -876,7 +881,8 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_hop_half_tm(Geom g, const void 
         constexpr bool XPRE = XR && ((WD_XR_PREFETCH >> PREC) & 1) && LF != WD_F64;
         cx<R> rpre[XPRE ? 12 : 1];
         if constexpr (XPRE)
-            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::load(rhs_view(xr.r, rhs), H, rpre);
+            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::template load<WD_NT_RLOAD>(
+                rhs_view(xr.r, rhs), H, rpre);
         const Nbrs nb = neighbours(g, site_of_half(g, H, p));
         cx<R> acc[12];
 #pragma unroll

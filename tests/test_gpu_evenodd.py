@@ -141,8 +141,10 @@ def test_evenodd_plus_kappa_solve(env):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f16"])
-def test_evenodd_batched_equals_single_bitwise(env, prec):
-    dims = (4, 4, 4, 8)
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (8, 8, 8, 8)])
+def test_evenodd_batched_equals_single_bitwise(env, prec, dims):
+    """(4,4,4,8) runs the one-lane-per-site half stencil, (8,8,8,8) the
+    marching one in float64."""
     U = gauge(dims, 95)
     B = synth.gaussian_sources(dims, [96, 97, 98, 99])
     rc, info, X = _solve(env, dims, U, B, 0.124, nrhs=4, tol=1e-11, prec=prec)
