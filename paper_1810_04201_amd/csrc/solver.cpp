@@ -103,6 +103,19 @@ static size_t field_bytes(int prec, int V, int nrhs) {
     return align256(field_data_bytes(prec, V, nrhs)) + 256;
 }
 
+// A^dag (A p) formed where r is updated (q never stored), and x += alpha p
+// moved into the p update (p read once for both): besides the stencils'
+// inputs an iteration moves 7 fields instead of 10.  Done by the marching
+// stencil on the full lattice and by the second half-field launch on the
+// even-odd form; WD_FUSE_XR=0 turns it off.
+static bool fused_iteration(const wd_lattice *lat, const wd_solve_params &p) {
+    const char *fx = getenv("WD_FUSE_XR");
+    if (fx && atoi(fx) == 0) return false;
+    if (p.form & WD_SOLVE_EVEN_ODD) return true;
+    return dslash_xr_supported(lat->g, p.prec_inner, p.nrhs,
+                               (int)reduce_partials_cap(lat->g, p.nrhs));
+}
+
 size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
     const bool eo = (p.form & WD_SOLVE_EVEN_ODD) != 0;
     const int V = eo ? lat->g.V / 2 : lat->g.V, nr = p.nrhs;
@@ -110,8 +123,10 @@ size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
     const int lo_xr = lo == WD_F16 ? WD_F32 : lo;
     // float64: b, b', x, r, t, Ax (+ b_o and an odd temporary for even-odd)
     size_t b = (eo ? 8 : 6) * field_bytes(WD_F64, V, nr);
-    // inner: x, r in lo_xr; p, t, Ap (+ an odd temporary) in lo
-    b += 2 * field_bytes(lo_xr, V, nr) + (eo ? 4 : 3) * field_bytes(lo, V, nr);
+    // inner: x, r in lo_xr; p, t (+ Ap unless the iteration is fused, + an
+    // odd temporary) in lo
+    const int nlo = 2 + (fused_iteration(lat, p) ? 0 : 1) + (eo ? 1 : 0);
+    b += 2 * field_bytes(lo_xr, V, nr) + nlo * field_bytes(lo, V, nr);
     b += align256((size_t)reduce_partials_cap(lat->g, p.nrhs) * sizeof(double));
     b += align256(sizeof(RhsState) * 12) + 256;
     return b;
@@ -162,11 +177,12 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
         tmp64_ = next(WD_F64);
     }
     const int lo_xr = prec_ == WD_F16 ? WD_F32 : prec_;
+    fuse_xr_ = fused_iteration(lat_, p_);
     xl_ = next(lo_xr);
     rl_ = next(lo_xr);
     pl_ = next(prec_);
     tl_ = next(prec_);
-    apl_ = next(prec_);
+    if (!fuse_xr_) apl_ = next(prec_);
     if (eo_) tmpl_ = next(prec_);
     partials_ = (double *)cur;
     partials_cap_ = (int)reduce_partials_cap(lat_->g, nrhs);
@@ -207,14 +223,6 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
     // are being timed; WD_GRAPH=0 turns it off.
     const char *ge = getenv("WD_GRAPH");
     use_graph_ = s_ != nullptr && !timing_enabled() && !(ge && atoi(ge) == 0);
-    // A^dag (A p) formed where r is updated (q never stored), and x += alpha p
-    // moved into the p update (p read once for both): besides the stencils'
-    // inputs an iteration moves 7 fields instead of 10.  Done by the
-    // marching stencil on the full lattice and by the second half-field
-    // launch on the even-odd form; WD_FUSE_XR=0 turns it off.
-    const char *fx = getenv("WD_FUSE_XR");
-    fuse_xr_ = !(fx && atoi(fx) == 0) &&
-               (eo_ || dslash_xr_supported(lat_->g, prec_, nrhs, partials_cap_));
     ctl_.lag_x = fuse_xr_ ? 1 : 0;
     return WD_OK;
 }
