@@ -50,7 +50,7 @@ FUSED_XR = os.environ.get("WD_FUSE_XR", "1") != "0"
 
 def f64_bytes(lat):
     """Per-site algorithmic bytes of the float64 marching stencil and of its
-    x/r-updating form on this lattice: its links are read as 12 reals (384
+    r-updating form on this lattice: its links are read as 12 reals (384
     bytes per site) when wd_set_gauge found them special unitary, else 18
     (576)."""
     link = 384 if lat.links_info()[0] == 12 else 576
@@ -98,7 +98,7 @@ def applications(info, prec_inner):
     """Stencil applications a solve performed, by kernel and precision (no-op
     launches enqueued after convergence do no work and are not counted).  An
     iteration applies the plain stencil once and, with the fused update, the
-    x/r-updating stencil once ("xr_" keys)."""
+    r-updating stencil once ("xr_" keys)."""
     it, up = info["iters"], info["reliable_updates"]
     out = {"f64": 1 + 2 * max(up - 1, 0) + 1}  # D^dag b, reliable updates, final D x
     out[prec_inner] = out.get(prec_inner, 0) + (it if FUSED_XR else 2 * it)
@@ -504,7 +504,7 @@ def even_odd(args, wd, lat, bd, kappa, stream, torch, V):
         res[f"{prec}_rel_resid_D"] = info[0]["rel_resid_D"]
         # half-field launches that did work in this precision (gated launches
         # that found nothing to do are timed too, so the average is an upper
-        # bound): 4 per inner iteration, the last of them x/r-updating when
+        # bound): 4 per inner iteration, the last of them r-updating when
         # fused; in float64 also b^ and M^dag b^ (3), 4 per reliable update
         # after the first, and the odd half and the final residual (3)
         fused = n_xr > 0
@@ -784,7 +784,7 @@ def pmc_summary(args):
     grp = {"f64": 1, "f32": 2, "f16": 2}
     kinds = []
     for i, prec in enumerate(("f64", "f32", "f16")):
-        # the plain stencil (D, no reduction) and the CG's x/r-updating D^dag;
+        # the plain stencil (D, no reduction) and the CG's r-updating D^dag;
         # float64 with its 12-real (form 3) or 18-real links
         forms = ((3, 384), (0, 576)) if prec == "f64" else ((i, None),)
         for lf, link in forms:

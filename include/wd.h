@@ -297,9 +297,9 @@ const char *wd_last_error(void);
  * stencil launch.  wd_timing_read returns the summed milliseconds and launch
  * count for one kernel family since the last reset; it synchronises the
  * pending events.  Families: "dslash_f64", "dslash_f32", "dslash_f16" (the
- * stencil), "dslash_xr_<prec>" (a CG iteration's second stencil with the x/r
- * update fused), "eo_<prec>" (half-field stencil of the even-odd form),
- * "halo_f64" (slab stencil).  Solver chunks are not captured into HIP graphs
+ * stencil), "dslash_xr_<prec>" (a CG iteration's second stencil with the r
+ * update fused), "eo_<prec>" and "eo_xr_<prec>" (half-field stencils of the
+ * even-odd form, plain and r-updating), "halo_f64" (slab stencil).  Solver chunks are not captured into HIP graphs
  * while timing is on. */
 int wd_timing_enable(int on);
 int wd_timing_reset(void);

@@ -1,7 +1,8 @@
 // Field kernels of the CG solve (Sec. 2.2): gauge and spinor packing between
 // the canonical interleaved layout and the internal planes, precision
-// conversion, the fused vector updates x += alpha p / r -= alpha Ap with the
-// |r|^2 reduction, p = r + beta p, the float64 true residual, and norms.
+// conversion, the vector updates of the CG iteration (x += alpha p with
+// p = r + beta p in one pass; the unfused x/r update with the |r|^2
+// reduction and p update), the float64 true residual, and norms.
 // All of them stream their operands once; the reductions are the
 // deterministic block reduction of device.hpp.
 #include "device.hpp"

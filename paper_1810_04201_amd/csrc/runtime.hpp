@@ -74,7 +74,7 @@ void hop_half(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs
               Gate gate, hipStream_t s);
 
 // hop_half with c present whose output q is consumed where it is formed
-// (x += alpha p, r -= alpha q; see launch_hop_half_xr)
+// (r -= alpha q; see launch_hop_half_xr)
 void hop_half_xr(wd_lattice *lat, void *const gh[2], int p, double kappa, double cs, int dagger,
                  const FieldRef &in, const FieldRef &c, const XrArgs &xr, const RedArgs &red,
                  Gate gate, hipStream_t s);
@@ -151,7 +151,7 @@ class Solve {
     int prec_;
     int d1_ = 0, d2_ = 1;  // daggers of the two operators of the normal equations
     bool eo_ = false;      // on the even-odd Schur complement
-    bool fuse_xr_ = false;  // the second operator application does the x/r update
+    bool fuse_xr_ = false;  // the second operator application updates r (x lags)
     int chunk_ = 8;
     int rel_every_ = 1;  // inner iterations between gated reliable updates
     bool use_graph_ = false;

@@ -1,13 +1,16 @@
 // Conjugate gradient on the normal equations (Sec. 2.2) as a resumable,
 // stream-ordered state machine.
 //
-// Per inner iteration four kernels run back to back on the solve's stream
+// Per inner iteration three kernels run back to back on the solve's stream
 // (CGNR; the CGNE form of the paper's listing exchanges D and D^dag, solves
 // D D^dag y = b from b' = b and returns x = D^dag y):
-//   t  = D p         (stencil, fused |t|^2 -> alpha = |r|^2 / |t|^2)
-//   Ap = D^dag t     (stencil)
-//   x += alpha p, r -= alpha Ap  (fused |r|^2 -> beta, convergence, triggers)
-//   p  = r + beta p
+//   t  = D p                        (stencil, fused |t|^2 -> alpha = |r|^2 / |t|^2)
+//   r -= alpha D^dag t              (stencil forming D^dag t where r is updated,
+//                                    fused |r|^2 -> beta, convergence, triggers)
+//   x += alpha p, p = r + beta p    (one pass over p)
+// (the unfused form stores Ap = D^dag t and runs the x/r and p updates as
+// two kernels).  On the even-odd form each stencil is two half-field
+// launches.
 // All scalars stay on the device (RhsState); the host only reads a small
 // status record every `chunk_` iterations and never stalls the stream on it:
 // inner iterations enqueued after an rhs froze are exact no-ops, so results
