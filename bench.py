@@ -307,7 +307,9 @@ def main():
     else:
         lat.close()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(np)
+        it16 = (out.get("extras", {}).get("small_configs", {}).get("16x16x16x32", {})
+                .get("cg_f64_iters"))
+        out["cpu_baseline"] = cpu_baseline(np, it16)
     print(json.dumps(out))
 
 
@@ -670,8 +672,10 @@ def serving(np, torch, synth, wd, n_requests):
     return res
 
 
-def cpu_baseline(np):
-    """The CPU oracle's stencil (NumPy, complex128) on 16^3 x 32, median of 3."""
+def cpu_baseline(np, iters_16=None):
+    """The CPU oracle's stencil (NumPy, complex128) on 16^3 x 32, median of 3;
+    its CG on the 4^4 configuration to solution; and 3 CG iterations on
+    16^3 x 32, extrapolated to the iteration count the GPU solve took."""
     import synth
     from oracle import wilson
     dims = (16, 16, 16, 32)
@@ -693,12 +697,22 @@ def cpu_baseline(np):
     _, it4, _ = cg.cgnr(lambda v: wilson.apply_D(U4, v, d4, 0.12),
                         lambda v: wilson.apply_Ddag(U4, v, d4, 0.12), b4, tol=1e-10)
     tc = time.time() - tc
-    return {"value": round(V * FLOP_PER_SITE / t / 1e9, 3), "unit": "GFLOP/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"oracle apply_D (NumPy einsum stencil, complex128) on 16^3x32, median of 3 "
-                      f"runs of {t:.2f}s; 1 thread used (einsum is single-threaded), "
-                      f"{os.cpu_count()} cores present",
-            "cg_4x4x4x4_s": round(tc, 4), "cg_4x4x4x4_iters": it4}
+    out = {"value": round(V * FLOP_PER_SITE / t / 1e9, 3), "unit": "GFLOP/s",
+           "cores": 1, "kind": "oracle",
+           "sample": f"oracle apply_D (NumPy einsum stencil, complex128) on 16^3x32, median of 3 "
+                     f"runs of {t:.2f}s; 1 thread used (einsum is single-threaded), "
+                     f"{os.cpu_count()} cores present",
+           "cg_4x4x4x4_s": round(tc, 4), "cg_4x4x4x4_iters": it4}
+    if iters_16:
+        b16 = synth.gaussian_spinor(dims, 102)
+        t3 = time.time()
+        cg.cgnr(lambda v: wilson.apply_D(U, v, dims, 0.124),
+                lambda v: wilson.apply_Ddag(U, v, dims, 0.124), b16, tol=1e-30, max_iter=3)
+        t3 = (time.time() - t3) / 3
+        out["cg_16x16x16x32_extrapolated_s"] = round(t3 * iters_16, 1)
+        out["cg_16x16x16x32_note"] = (f"3 oracle CG iterations ({t3:.2f} s each, D^dag b "
+                                      f"included) times the GPU solve's {iters_16}")
+    return out
 
 
 # ------------------------------------------------------------------ profiling helpers
