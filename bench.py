@@ -81,6 +81,7 @@ def parse():
     ap.add_argument("--probe", action="store_true")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="STATS_CSV")
+    ap.add_argument("--valu-summary", metavar="PMC_CSV")
     ap.add_argument("--out")
     ap.add_argument("--cmd", default="")
     return ap.parse_args()
@@ -130,6 +131,8 @@ def main():
         return pmc_summary(args)
     if args.trace_summary:
         return trace_summary(args)
+    if args.valu_summary:
+        return valu_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                           "(the multi-GPU halo-exchange path is a design, not built)"}))
@@ -764,6 +767,24 @@ def probe(np, torch, synth, wd):
         torch.cuda.synchronize()
         print(f"probe cg {prec} done", flush=True)
     lat.close()
+    del psi, out, x
+    torch.cuda.empty_cache()
+    # the batched stencil: 12 sources on 24^3 x 48, FP32-12
+    dims = (24, 24, 24, 48)
+    V = int(np.prod(dims))
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.gauge(dims, 4, synth.EXP, 0.3)).to(dev))
+    B = torch.from_numpy(synth.gaussian_sources(dims, list(range(200, 212)))).to(dev)
+    fa = wd.Field(lat, "f32", nrhs=12)
+    fb = wd.Field(lat, "f32", nrhs=12)
+    fa.load(B)
+    for _ in range(3):
+        wd.wd_dslash(lat, 0.124, 0, fa, fb)
+    torch.cuda.synchronize()
+    fa.close()
+    fb.close()
+    lat.close()
+    print("probe nrhs=12 done", flush=True)
 
 
 def _pmc_rows(path):
@@ -814,6 +835,10 @@ def pmc_summary(args):
         wr = [r for r in write if tag in r["name"]]
         if not fr or not wr:
             continue
+        # the 48^3 x 96 launches (the batched probe on 24^3 x 48 has another
+        # launch shape and comes later)
+        fr = [r for r in fr if r["grid"] == fr[0]["grid"]]
+        wr = [r for r in wr if r["grid"] == wr[0]["grid"]]
         # launches that did work (a solve's launches after it stopped return
         # at once)
         fm = max(r["FETCH_SIZE"] for r in fr)
@@ -829,6 +854,21 @@ def pmc_summary(args):
             "algorithmic_bytes": alg, "algorithmic_bytes_per_site": bps,
             "traffic_over_algorithmic": round(traffic / alg, 3),
             "traffic_bytes_per_site": round(traffic / V, 1)}
+    # the batched FP32 stencil, 12 sources on 24^3 x 48: bytes per rhs-site
+    tag = "k_dslash_tm<1, false, false, 2, false, false, 1>"
+    fr = [r for r in fetch if tag in r["name"]]
+    wr = [r for r in write if tag in r["name"]]
+    if fr and wr and fr[-1]["grid"] != fr[0]["grid"]:
+        g12 = fr[-1]["grid"]
+        fk = statistics.median(r["FETCH_SIZE"] for r in fr if r["grid"] == g12)
+        wk = statistics.median(r["WRITE_SIZE"] for r in wr if r["grid"] == g12)
+        n = 24 * 24 * 24 * 48 * 12
+        out["kernels"]["dslash_f32_nrhs12_24x24x24x48"] = {
+            "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk,
+            "traffic_bytes": round(fk * 1024 * ff + wk * 1024 * wf),
+            "algorithmic_bytes_per_rhs_site": 208,
+            "fetch_bytes_per_rhs_site": round(fk * 1024 * ff / n, 1),
+            "write_bytes_per_rhs_site": round(wk * 1024 * wf / n, 1)}
     # even-odd half-field stencil (k_hop_half): a launch writes V/2 sites,
     # reads every link once and the other half's spinors, and (every second
     # launch of M) a c field
@@ -858,6 +898,39 @@ def pmc_summary(args):
         json.dump(out, f, indent=1)
         f.write("\n")
     print(json.dumps(out))
+
+
+def valu_summary(args):
+    """Vector-ALU instructions of the probe's stencil launches (SQ_INSTS_VALU,
+    wave instructions) and the time the chip needs just to issue them: four
+    cycles per wave64 instruction on each of 1024 SIMDs at 2.4 GHz (no packed
+    FP32).  Compared with a launch's duration this says how close to
+    ALU-bound it is."""
+    rows = _pmc_rows(args.valu_summary)
+    lines = ["# Vector-ALU work of the stencil launches", "", f"Command: `{args.cmd}`", "",
+             "Issue time: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz), the least time "
+             "the chip needs to issue the launch's vector instructions; the launch durations "
+             "are in the kernel statistics and the bench line (e.g. FP64 stencil 1.93 ms, "
+             "binary16 0.65 ms, the 12-source FP32 stencil 0.57 ms).", "",
+             "| kernel | launch shape (threads) | VALU wave-instr. | issue time ms |",
+             "|---|---|---|---|"]
+    # per kernel and launch shape, the launch that did the most work (a
+    # solve's launches after it stopped return at once)
+    best = {}
+    for r in rows:
+        if "k_dslash_tm" not in r["name"] and "k_hop_half" not in r["name"]:
+            continue
+        key = (r["name"], r["grid"])
+        if r.get("SQ_INSTS_VALU", 0.0) >= best.get(key, {}).get("SQ_INSTS_VALU", -1.0):
+            best[key] = r
+    for (_, _), r in best.items():
+        valu = r.get("SQ_INSTS_VALU", 0.0)
+        name = r["name"].split("(")[0].replace("void wd::", "")
+        lines.append(f"| `{name}` | {r['grid']} | {valu / 1e6:.1f} M | "
+                     f"{valu * 4 / (1024 * 2.4e9) * 1e3:.3f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def trace_summary(args):
