@@ -355,3 +355,41 @@ def test_fp64_iterate_after_max_iter_equals_oracle_iterate(env, monkeypatch, fus
 def _oracle_n(dims, U, b, kappa, n):
     return cg.cgnr(lambda v: wilson.apply_D(U, v, dims, kappa),
                    lambda v: wilson.apply_Ddag(U, v, dims, kappa), b, tol=1e-30, max_iter=n)
+
+
+def test_full_size_solves_residual_by_oracle_samples(env):
+    """The bench workload at full size: 48^3 x 96, kappa 0.1245, eps = 0.3
+    links seed 3, Gaussian source seed 103.  FP64, mixed FP16 and even-odd
+    FP64 solves to 1e-10; the oracle computes (D x)(s) from the GPU's x at
+    3000 sampled sites (boundary corners included), and the sampled
+    ||b - D x|| / ||b|| must agree with the GPU's own rel_resid_D within a
+    factor 2 and stay below 1e-9."""
+    torch, dev, wd = env
+    dims = (48, 48, 48, 96)
+    V = vol(dims)
+    print("full-size solves 48^3x96: generating links", flush=True)
+    U = gauge(dims, 3)
+    b = synth.gaussian_spinor(dims, 103)
+    lat = wd.Lattice(dims)
+    Ud = torch.from_numpy(U).to(dev)
+    lat.set_gauge(Ud)
+    del Ud
+    bd = torch.from_numpy(b).to(dev)
+    Uc = wilson.to_complex(U)
+    bc = wilson.to_complex(b)
+    rng = np.random.default_rng(11)
+    corners = [0, V - 1, 47, 48 * 47, 48 * 48 * 47, 48 ** 3 * 95, 48 ** 3 - 1, 48 ** 3]
+    sites = np.concatenate([corners, rng.integers(0, V, 2992)])
+    for prec, eo in (("f64", False), ("f16", False), ("f64", True)):
+        print(f"  prec={prec} even_odd={eo}", flush=True)
+        x = torch.zeros_like(bd)
+        rc, info = lat.solve(bd, x, 0.1245, tol=1e-10, prec=prec, even_odd=eo)
+        torch.cuda.synchronize()
+        assert rc == 0 and info[0]["true_rel_resid"] <= 1e-10, info
+        xc = wilson.to_complex(x.cpu().numpy())
+        dx = wilson.apply_D_sites(lambda s: Uc[s], lambda s: xc[s], dims, 0.1245, sites)
+        r = bc[sites] - dx
+        est = float(np.sqrt(np.sum(np.abs(r) ** 2) / np.sum(np.abs(bc[sites]) ** 2)))
+        assert est <= 1e-9
+        assert 0.5 <= est / info[0]["rel_resid_D"] <= 2.0, (est, info[0]["rel_resid_D"])
+    lat.close()
