@@ -133,6 +133,24 @@ def test_dslash_384_site_bricks(torch_dev, wd, monkeypatch, prec, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_dslash_bricks_larger_than_a_workgroup(torch_dev, wd, monkeypatch, prec):
+    """Bricks of 16x8x6 = 768 sites: every precision marches the brick slice
+    in several parts (float64 two of 384, the float kernels three of 256),
+    neighbours across parts and faces from memory.  Parity with the oracle,
+    D and D^dag, 2 rhs."""
+    torch, dev = torch_dev
+    monkeypatch.setenv("WD_BRICK", "16,8,6")
+    dims = (16, 8, 12, 4)
+    U = gauge(dims, 25, "exp")
+    psi = synth.gaussian_sources(dims, [26, 27])
+    for dagger in (0, 1):
+        got = _apply(wd, torch, dev, dims, U, psi, 0.1245, prec, dagger, nrhs=2).reshape(psi.shape)
+        op = wilson.apply_Ddag if dagger else wilson.apply_D
+        for k in range(2):
+            assert site_rel_err(got[k], op(U, psi[k], dims, 0.1245)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_plus_kappa_lattice(torch_dev, wd, prec):
     """WD_SIGN_PLUS_KAPPA: D = 1 + kappa (hops) as printed in Eq. (1)."""
     torch, dev = torch_dev

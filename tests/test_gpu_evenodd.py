@@ -282,12 +282,13 @@ def test_schur_after_gauge_form_changes(env):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("dims,brick", [((8, 8, 8, 8), None), ((8, 8, 12, 6), "8,8,6"),
-                                        ((16, 8, 8, 4), "16,8,2")])
+                                        ((16, 8, 8, 4), "16,8,2"), ((16, 8, 8, 4), "16,8,8")])
 def test_marching_half_stencil_equals_site_form(env, monkeypatch, prec, dims, brick):
     """The marching half-field stencil (half slices of 64-multiples staged in
     LDS; float64 and float32) against the one-lane-per-site form
     (WD_EO_SITE=1): the same hops in the same order, so M and M^dag agree to
-    the last bits, with 3 rhs."""
+    the last bits, with 3 rhs.  16x8x8 bricks (512 sites per parity) take two
+    parts per half slice."""
     torch, dev, wd = env
     if brick:
         monkeypatch.setenv("WD_BRICK", brick)
