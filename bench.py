@@ -377,10 +377,17 @@ def slab_share(np, torch, synth, wd):
     plain = timeit(lambda: wd.wd_dslash(lat, 0.1245, 0, fa, fb))
     pack = timeit(lambda: wd.wd_halo_pack(lat, fa, sp, sn))
     halo = timeit(lambda: wd.wd_dslash_halo(lat, 0.1245, fa, fb, sn, sp, False, False))
+    # the split a multi-GPU run overlaps with the face transfer: interior
+    # chunks first (no face read), then the chunks holding the slab ends
+    inner = timeit(lambda: wd.wd_dslash_halo(lat, 0.1245, fa, fb, None, None, False, False,
+                                             region="interior"))
+    ends = timeit(lambda: wd.wd_dslash_halo(lat, 0.1245, fa, fb, sn, sp, False, False,
+                                            region="ends"))
     face_bytes = n * 8
     res = {"lattice": "48x48x48x12 (one of 8 t-slabs of 48x48x48x96)",
            "dslash_plain_ms": round(plain, 4), "halo_pack_ms": round(pack, 4),
            "dslash_halo_ms": round(halo, 4),
+           "dslash_halo_interior_ms": round(inner, 4), "dslash_halo_ends_ms": round(ends, 4),
            "dslash_halo_GBps_algorithmic": round(V * f64_bytes(lat)[0] / halo / 1e6, 1),
            "face_bytes_per_direction": face_bytes,
            "face_over_xgmi_link_us_estimate": round(face_bytes / 153e9 * 1e6, 1)}

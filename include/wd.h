@@ -194,13 +194,25 @@ int wd_dslash(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_
  *                      global t = 0 / t = T-1, where the antiperiodic sign
  *                      applies.  A single slab with its own faces and
  *                      WD_HALO_FIRST | WD_HALO_LAST is the whole lattice.
+ *                      WD_HALO_INTERIOR computes only the slab's interior
+ *                      chunks of t slices (those holding neither its first
+ *                      nor its last slice) and reads no face, so it may run
+ *                      while the faces are in flight (recv_prev / recv_next
+ *                      may be NULL); WD_HALO_ENDS then computes the rest.
+ *                      The two together write what one call without either
+ *                      flag writes, bit for bit.
  * Faces (device, caller-owned): per rhs 6 planes of V/Lt complex float64 (the
  * projected half-spinor of a boundary slice, 96 bytes per face site), sites
  * in the library's internal face order, the same on every slab of one shape.
  * Float64 fields; lattices whose bricks are whole multiples of 64 sites (the
  * marching stencil).  Stream-ordered; wd_dslash_halo allocates its staging
  * stream-ordered. */
-enum { WD_HALO_FIRST = 1u << 0, WD_HALO_LAST = 1u << 1 };
+enum {
+    WD_HALO_FIRST = 1u << 0,
+    WD_HALO_LAST = 1u << 1,
+    WD_HALO_INTERIOR = 1u << 2,
+    WD_HALO_ENDS = 1u << 3
+};
 int wd_set_halo_gauge(wd_lattice *lat, const double *U_prev, void *stream);
 int wd_halo_pack(wd_lattice *lat, int dagger, const wd_field *in, double *send_prev,
                  double *send_next, void *stream);

@@ -41,7 +41,8 @@ WD_BC_ANTIPERIODIC_T = 1
 WD_SIGN_PLUS_KAPPA = 2
 WD_FORM_CGNR, WD_FORM_CGNE = 0, 1
 WD_SOLVE_EVEN_ODD = 1 << 8
-WD_HALO_FIRST, WD_HALO_LAST = 1, 2
+WD_HALO_FIRST, WD_HALO_LAST, WD_HALO_INTERIOR, WD_HALO_ENDS = 1, 2, 4, 8
+HALO_REGION = {"all": 0, "interior": WD_HALO_INTERIOR, "ends": WD_HALO_ENDS}
 FORM = {"cgnr": WD_FORM_CGNR, "cgne": WD_FORM_CGNE, WD_FORM_CGNR: WD_FORM_CGNR,
         WD_FORM_CGNE: WD_FORM_CGNE}
 
@@ -233,12 +234,15 @@ def wd_halo_pack(lattice, field, send_prev, send_next, dagger=False, stream=None
 
 
 def wd_dslash_halo(lattice, kappa, fin, fout, recv_prev, recv_next, first, last, dagger=False,
-                   stream=None):
+                   stream=None, region="all"):
+    """region: "all", "interior" (no face read; recv_* may be None) or
+    "ends" (the chunks holding the slab's first and last slices)."""
     n = face_numel(lattice, fin.nrhs)
-    flags = (WD_HALO_FIRST if first else 0) | (WD_HALO_LAST if last else 0)
+    flags = (WD_HALO_FIRST if first else 0) | (WD_HALO_LAST if last else 0) | HALO_REGION[region]
+    rp = None if recv_prev is None else _dptr(recv_prev, n, "recv_prev")
+    rn = None if recv_next is None else _dptr(recv_next, n, "recv_next")
     _check(lib.wd_dslash_halo(lattice.handle, float(kappa), 1 if dagger else 0, fin.handle,
-                              fout.handle, _dptr(recv_prev, n, "recv_prev"),
-                              _dptr(recv_next, n, "recv_next"), flags, _stream(stream)))
+                              fout.handle, rp, rn, flags, _stream(stream)))
 
 
 def wd_apply_D(h, kappa, prec, inp, out, volume, stream=None):

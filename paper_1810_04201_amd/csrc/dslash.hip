@@ -393,8 +393,9 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
     const FieldRef fin = rhs_view(in, rhs), fout = rhs_view(out, rhs);
     const int cc = cb / nsub;
     const int h = cb - cc * nsub;
-    const int chunk = cc / ncols;
-    const int col = cc - chunk * ncols;
+    const int lchunk = cc / ncols;
+    const int col = cc - lchunk * ncols;
+    const int chunk = HALO ? halo.cfirst + lchunk * halo.cstep : lchunk;
     const int Lt = g.L[3], bvol = g.bvol;
     const int l = (int)threadIdx.x;
     const int t0 = chunk * tchunk;
@@ -590,7 +591,7 @@ static void launch_tm_k(dim3 grid, dim3 bs, size_t lds, hipStream_t s, const Geo
     auto k = k_dslash_tm<PREC, DAG, RED, G, false, false, LF>;
     allow_lds(k, lds);
     hipLaunchKernelGGL(k, grid, bs, lds, s, g, gauge, in, out, kappa, r, gate, tch, ncols,
-                       Halo{nullptr, nullptr, nullptr, 0, 0}, XrArgs{});
+                       Halo{nullptr, nullptr, nullptr, 0, 0, 0, 0, 1}, XrArgs{});
 }
 
 template <int PREC, int LF = PREC>
@@ -687,7 +688,7 @@ static bool xr_prec(const Geom &g, const void *gauge, double kappa, int dagger, 
     const dim3 grid(tm_blocks(g, tch) * nsub * in.nrhs), bs(wvol);
     const size_t lds = 2 * slice_bytes<PREC>(wvol);
     constexpr int G = HopGroup<PREC>::value;
-    const Halo nh{nullptr, nullptr, nullptr, 0, 0};
+    const Halo nh{nullptr, nullptr, nullptr, 0, 0, 0, 0, 1};
     if (dagger) {
         auto k = k_dslash_tm<PREC, true, true, G, false, true, LF>;
         allow_lds(k, lds);
@@ -1179,12 +1180,27 @@ bool halo_supported(const Geom &g) { return tm_eligible(g) && tm_fits<WD_F64>(g)
 
 template <int LF>
 static void launch_halo_lf(const Geom &g, const void *gauge, double kappa, int dagger,
-                           FieldRef in, FieldRef out, const Halo &halo, hipStream_t s) {
+                           FieldRef in, FieldRef out, const Halo &region, hipStream_t s) {
     const int wvol = tm_wvol(g, WD_F64);
     const int nsub = g.bvol / wvol;
     const int tch = tm_chunk(g, in.nrhs * nsub);
     const int ncols = g.V / (g.L[3] * g.bvol);
-    const dim3 grid(tm_blocks(g, tch) * nsub * in.nrhs), bs(wvol);
+    // chunks of this launch: all; the interior ones (neither slice 0 nor
+    // Lt - 1: no staged face is read); or the one or two holding the ends
+    const int nch = (g.L[3] + tch - 1) / tch;
+    Halo halo = region;
+    int count = nch;
+    halo.cfirst = 0;
+    halo.cstep = 1;
+    if (region.region == 1) {
+        count = nch - 2;
+        halo.cfirst = 1;
+    } else if (region.region == 2) {
+        count = nch < 2 ? nch : 2;
+        halo.cstep = nch - 1 > 0 ? nch - 1 : 1;
+    }
+    if (count <= 0) return;
+    const dim3 grid(ncols * count * nsub * in.nrhs), bs(wvol);
     const size_t lds = 2 * slice_bytes<WD_F64>(wvol);
     constexpr int G = HopGroup<WD_F64>::value;
     const Gate none{nullptr, nullptr, GATE_ACTIVE};

@@ -548,7 +548,9 @@ int wd_halo_pack(wd_lattice *lat, int dagger, const wd_field *in, double *send_p
 int wd_dslash_halo(wd_lattice *lat, double kappa, int dagger, const wd_field *in, wd_field *out,
                    const double *recv_prev, const double *recv_next, uint32_t flags,
                    void *stream) {
-    if (!lat || !in || !out || !recv_prev || !recv_next) return fail(WD_ERR_ARG, "null argument");
+    const bool interior = (flags & WD_HALO_INTERIOR) != 0;
+    if (!lat || !in || !out || (!interior && (!recv_prev || !recv_next)))
+        return fail(WD_ERR_ARG, "null argument");
     if (in == out) return fail(WD_ERR_ARG, "in and out must be different fields");
     if (in->lat != lat || out->lat != lat) return fail(WD_ERR_ARG, "fields of another lattice");
     if (in->prec != WD_F64 || out->prec != WD_F64)
@@ -556,14 +558,29 @@ int wd_dslash_halo(wd_lattice *lat, double kappa, int dagger, const wd_field *in
     if (in->nrhs != out->nrhs) return fail(WD_ERR_ARG, "in/out nrhs differ");
     if (!std::isfinite(kappa)) return fail(WD_ERR_ARG, "kappa not finite");
     if (dagger != 0 && dagger != 1) return fail(WD_ERR_ARG, "dagger must be 0 or 1");
-    if (flags & ~(uint32_t)(WD_HALO_FIRST | WD_HALO_LAST))
+    if (flags & ~(uint32_t)(WD_HALO_FIRST | WD_HALO_LAST | WD_HALO_INTERIOR | WD_HALO_ENDS))
         return fail(WD_ERR_ARG, "unknown halo flags 0x%x", flags);
+    if (interior && (flags & WD_HALO_ENDS))
+        return fail(WD_ERR_ARG, "WD_HALO_INTERIOR and WD_HALO_ENDS exclude each other");
     if (!halo_supported(lat->g))
         return fail(WD_ERR_ARG, "halo exchange needs the marching stencil (bricks of a multiple "
                                 "of 64 sites)");
     if (!lat->has_gauge) return fail(WD_ERR_NOGAUGE, "gauge field not set");
     if (!lat->halo_links) return fail(WD_ERR_STATE, "halo links not set (wd_set_halo_gauge)");
     hipStream_t s = (hipStream_t)stream;
+    const int region = interior ? 1 : ((flags & WD_HALO_ENDS) ? 2 : 0);
+    const double k = -lat->hop_sign * kappa;
+    if (interior) {
+        // no staged face is read: the faces need not have arrived
+        const Halo halo{nullptr, nullptr, lat->halo_links, (flags & WD_HALO_FIRST) ? 1 : 0,
+                        (flags & WD_HALO_LAST) ? 1 : 0, region, 0, 1};
+        timed("halo_f64", s, [&] {
+            launch_dslash_halo(lat->g, lat->gauge[WD_F64], k, dagger, in->ref, out->ref, halo, s,
+                               lat->gauge12);
+        });
+        WD_LAUNCH_CHECK();
+        return WD_OK;
+    }
     const int vf = lat->g.V / lat->g.L[3];
     const size_t one = field_data_bytes(WD_F64, vf, in->nrhs) + 256;
     void *mem = nullptr;
@@ -578,8 +595,7 @@ int wd_dslash_halo(wd_lattice *lat, double kappa, int dagger, const wd_field *in
     launch_halo_stage(lat->g, recv_prev, sp, s);
     launch_halo_stage(lat->g, recv_next, sn, s);
     const Halo halo{sp.data, sn.data, lat->halo_links, (flags & WD_HALO_FIRST) ? 1 : 0,
-                    (flags & WD_HALO_LAST) ? 1 : 0};
-    const double k = -lat->hop_sign * kappa;
+                    (flags & WD_HALO_LAST) ? 1 : 0, region, 0, 1};
     timed("halo_f64", s, [&] {
         launch_dslash_halo(lat->g, lat->gauge[WD_F64], k, dagger, in->ref, out->ref, halo, s,
                            lat->gauge12);

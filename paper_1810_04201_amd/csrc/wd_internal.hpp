@@ -272,6 +272,10 @@ struct Halo {
     const void *next;
     const void *links;
     int first, last;
+    // the chunks of t slices a launch covers: chunk cfirst + k * cstep for
+    // the launch's k-th chunk (all chunks: 0, 1); region selects them in
+    // launch_dslash_halo (0 all, 1 interior, 2 the two holding the slab ends)
+    int region, cfirst, cstep;
 };
 
 struct SolveCtl {

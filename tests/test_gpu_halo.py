@@ -142,3 +142,57 @@ def test_halo_argument_errors(env):
     f.close()
     g.close()
     lat.close()
+
+
+@pytest.mark.parametrize("dims,nslab", [((8, 8, 8, 32), 2), ((4, 4, 8, 16), 1)])
+def test_interior_then_ends_equals_whole_slab_bitwise(env, dims, nslab):
+    """The interior chunks (computed with no faces at all) and then the end
+    chunks write exactly what one whole-slab call writes, and NaN faces given
+    to the interior call cannot reach its output."""
+    torch, dev, wd = env
+    lx, ly, lz, lt = dims
+    lts = lt // nslab
+    vs = lx * ly * lz
+    U = gauge(dims, 119)
+    psi = synth.gaussian_spinor(dims, 120)
+    sl = slice(0, lts * vs)
+    lat = wd.Lattice((lx, ly, lz, lts))
+    lat.set_gauge(torch.from_numpy(np.ascontiguousarray(U[sl])).to(dev))
+    tprev = lt - 1
+    wd.wd_set_halo_gauge(lat, torch.from_numpy(
+        np.ascontiguousarray(U[tprev * vs:(tprev + 1) * vs, 3])).to(dev))
+    fi = wd.Field(lat, "f64")
+    fi.load(torch.from_numpy(np.ascontiguousarray(psi[sl])).to(dev))
+    n = wd.face_numel(lat)
+    sp = torch.empty(n, dtype=torch.float64, device=dev)
+    sn = torch.empty(n, dtype=torch.float64, device=dev)
+    wd.wd_halo_pack(lat, fi, sp, sn)
+    outs = []
+    for split in (False, True):
+        fo = wd.Field(lat, "f64")
+        o = torch.full((lts * vs, 4, 3, 2), float("nan"), dtype=torch.float64, device=dev)
+        fo.load(o)
+        if split:
+            nan = torch.full_like(sp, float("nan"))
+            wd.wd_dslash_halo(lat, 0.1245, fi, fo, None, nan, True, nslab == 1,
+                              region="interior")
+            wd.wd_dslash_halo(lat, 0.1245, fi, fo, sn, sp, True, nslab == 1, region="ends")
+        else:
+            wd.wd_dslash_halo(lat, 0.1245, fi, fo, sn, sp, True, nslab == 1)
+        fo.store(o)
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy())
+        fo.close()
+    assert np.all(np.isfinite(outs[1]))
+    assert np.array_equal(outs[0], outs[1])
+    fo = wd.Field(lat, "f64")
+    with pytest.raises(wd.WdError, match="exclude"):
+        wd.wd_dslash_halo(lat, 0.1, fi, fo, None, None, True, True, region="interior")
+        wd._check(wd.lib.wd_dslash_halo(lat.handle, 0.1, 0, fi.handle, fo.handle, None, None,
+                                        wd.WD_HALO_INTERIOR | wd.WD_HALO_ENDS, None))
+    with pytest.raises(wd.WdError, match="null"):
+        wd._check(wd.lib.wd_dslash_halo(lat.handle, 0.1, 0, fi.handle, fo.handle, None, None,
+                                        wd.WD_HALO_ENDS, None))
+    fo.close()
+    fi.close()
+    lat.close()
