@@ -337,28 +337,31 @@ constexpr int kTmMaxBlock = WD_TM_MAXB;
 // sites (tm_wvol)
 inline bool tm_eligible(const Geom &g) { return g.bvol % 64 == 0; }
 
-// sites per marching workgroup: a contiguous part of a brick slice (a
-// multiple of 64 dividing bvol).  float64 takes up to 384 (one workgroup per CU holds its
-// two LDS slice images); the float kernels run four waves per SIMD and do
-// best with at most 256.
-inline int tm_wvol(const Geom &g, int prec) {
+// sites per marching workgroup: a contiguous part of n sites of a brick
+// slice (a multiple of 64 dividing n).  float64 takes parts of 192 where they
+// divide n: two such workgroups, each with two 36 KiB LDS slice images, share
+// a CU and fill each other's per-step barrier waits (measured at 48^3 x 96
+// against whole 384-site slices, one workgroup per CU); else up to 384.  The
+// float kernels run four waves per SIMD and do best with at most 256.
+inline int part_sites(int n, int prec) {
+    if (prec == WD_F64 && n % 192 == 0) return 192;
     const int cap = prec == WD_F64 ? 384 : 256;
-    if (g.bvol <= cap) return g.bvol;
-    // the largest multiple of 64 within the cap that divides the brick
+    if (n <= cap) return n;
+    // the largest multiple of 64 within the cap that divides n
     for (int w = cap - cap % 64; w >= 64; w -= 64)
-        if (g.bvol % w == 0) return w;
-    return g.bvol;
+        if (n % w == 0) return w;
+    return n;
 }
 
-// entries per workgroup of the marching half-field stencil: the largest
-// multiple of 64 within the full stencil's cap that divides a half slice
-// (bvol / 2 entries of one parity); 0 where a half slice is not whole tiles
+inline int tm_wvol(const Geom &g, int prec) { return part_sites(g.bvol, prec); }
+
+// entries per workgroup of the marching half-field stencil: the same rule
+// on a half slice (bvol / 2 entries of one parity); 0 where a half slice is
+// not whole tiles
 inline int eo_wvol(const Geom &g, int prec) {
     const int hvol = g.bvol / 2;
-    const int cap = prec == WD_F64 ? 384 : 256;
-    for (int w = cap; w >= 64; w -= 64)
-        if (hvol % w == 0) return w;
-    return 0;
+    if (hvol % 64) return 0;
+    return part_sites(hvol, prec);
 }
 
 // time slices per chunk: enough workgroups over all rhs to fill the chip (a
@@ -396,13 +399,14 @@ inline int64_t reduce_partials_cap(const Geom &g, int nrhs) {
 
 // Brick extents.  Preferred: whole x rows (the x neighbours and the
 // backward x links stay inside the brick), then the largest volume that is a
-// multiple of 64 (a brick slice is whole tiles): 384 sites where the lattice
-// has at least 256 brick columns to spread over the chip (float64 then
-// marches a whole 384-site slice per workgroup, the float kernels halves of
-// it: measured fastest at 48^3 x 96), else at most 256; then the fewest
-// neighbours across y/z brick faces per site (2/ty + 2/tz for a split
-// direction), then the thinner y extent.  Lattices too small for a 64-site
-// brick take whole x rows with the largest y/z divisors up to 8 and 4.
+// multiple of 64 (a brick slice is whole tiles): 768 sites where the lattice
+// has at least 128 such brick columns to spread over the chip (48^3 x 96:
+// float64 marches four 192-site parts of each slice, the float kernels three
+// of 256; measured 2-4% faster than 384-site bricks), else at most 256; then
+// the fewest neighbours per site outside the float64 workgroup's part of the
+// slice (brick faces, and the boundaries between parts), then the thinner y
+// extent.  Lattices too small for a 64-site brick take whole x rows with the
+// largest y/z divisors up to 8 and 4.
 // WD_BRICK="tx,ty,tz" overrides the choice (tuning).
 inline int largest_divisor_le(int n, int cap) {
     for (int d = cap < n ? cap : n; d >= 1; --d)
@@ -410,10 +414,35 @@ inline int largest_divisor_le(int n, int cap) {
     return 1;
 }
 
+// neighbours (x, y, z; both ways) that a brick slice of a x b x c sites in
+// parts of w consecutive local sites reads from outside each site's own part,
+// times 240 / (a b c): a direction the brick spans whole wraps inside it
+inline int part_faces(const int L[4], int a, int b, int c, int w) {
+    const int e[3] = {a, b, c};
+    long long out = 0;
+    for (int s = 0; s < a * b * c; ++s) {
+        const int q[3] = {s % a, (s / a) % b, s / (a * b)};
+        for (int d = 0; d < 3; ++d)
+            for (int step = -1; step <= 1; step += 2) {
+                int r[3] = {q[0], q[1], q[2]};
+                r[d] += step;
+                if (r[d] < 0 || r[d] >= e[d]) {
+                    if (e[d] < L[d]) {
+                        ++out;  // a brick face
+                        continue;
+                    }
+                    r[d] = (r[d] + e[d]) % e[d];
+                }
+                if ((r[0] + a * (r[1] + b * r[2])) / w != s / w) ++out;
+            }
+    }
+    return (int)(out * 240 / (a * b * c));
+}
+
 inline void choose_bricks(Geom &g) {
     int bx = 0, by = 0, bz = 0;
     long long best = 0;
-    const bool big_ok = (long long)g.V / ((long long)g.L[3] * 384) >= 256;
+    const bool big_ok = (long long)g.V / ((long long)g.L[3] * 768) >= 128;
     for (int a = 1; a <= g.L[0]; ++a) {
         if (g.L[0] % a) continue;
         for (int b = 1; b <= g.L[1]; ++b) {
@@ -421,10 +450,9 @@ inline void choose_bricks(Geom &g) {
             for (int c = 1; c <= g.L[2]; ++c) {
                 if (g.L[2] % c) continue;
                 const int v = a * b * c;
-                if (v % 64 || (v > 256 && !(v == 384 && big_ok))) continue;
+                if (v % 64 || (v > 256 && !(v == 768 && big_ok))) continue;
                 if (a & 1) continue;  // even-odd halves pair x neighbours
-                const int faces = (a < g.L[0] ? 240 / a : 0) + (b < g.L[1] ? 240 / b : 0) +
-                                  (c < g.L[2] ? 240 / c : 0);
+                const int faces = part_faces(g.L, a, b, c, part_sites(v, WD_F64));
                 const long long score = (a == g.L[0] ? (1LL << 40) : 0) + ((long long)v << 20) +
                                         (long long)(2048 - faces) * 128 + (127 - b);
                 if (score > best) {

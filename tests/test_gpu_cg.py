@@ -137,8 +137,8 @@ def test_multi_rhs_column_equals_single_bitwise(env, dims, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f16"])
 def test_cg_384_site_bricks(env, monkeypatch, prec):
-    """CG with 8x8x6 bricks (marching parts of 384 or 192 sites, one partial
-    sum per part of a slice): solution against the oracle."""
+    """CG with 8x8x6 bricks (marching parts of 192 sites, two per slice, one
+    partial sum per part): solution against the oracle."""
     monkeypatch.setenv("WD_BRICK", "8,8,6")
     dims = (8, 8, 12, 6)
     print(f"cg 384-site bricks prec={prec}", flush=True)

@@ -114,9 +114,9 @@ def test_dslash_multi_rhs(torch_dev, wd, nrhs, prec):
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("nrhs", [1, 3])
 def test_dslash_384_site_bricks(torch_dev, wd, monkeypatch, prec, nrhs):
-    """Bricks of 8x8x6 = 384 sites: float64 marches whole brick slices, the
-    float kernels two 192-site parts of each (neighbours across the parts come
-    from memory).  Full parity with the oracle, D and D^dag, 1 and 3 rhs."""
+    """Bricks of 8x8x6 = 384 sites: every precision marches two 192-site
+    parts of each brick slice (neighbours across the parts come from memory).
+    Full parity with the oracle, D and D^dag, 1 and 3 rhs."""
     torch, dev = torch_dev
     monkeypatch.setenv("WD_BRICK", "8,8,6")
     dims = (8, 8, 12, 6)
@@ -135,7 +135,7 @@ def test_dslash_384_site_bricks(torch_dev, wd, monkeypatch, prec, nrhs):
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_dslash_bricks_larger_than_a_workgroup(torch_dev, wd, monkeypatch, prec):
     """Bricks of 16x8x6 = 768 sites: every precision marches the brick slice
-    in several parts (float64 two of 384, the float kernels three of 256),
+    in several parts (float64 four of 192, the float kernels three of 256),
     neighbours across parts and faces from memory.  Parity with the oracle,
     D and D^dag, 2 rhs."""
     torch, dev = torch_dev
