@@ -143,8 +143,43 @@ static int check_choice(int Lx, int Ly, int Lz, int Lt) {
     return fails;
 }
 
+// neighbours read from outside a site's part, against the closed forms for
+// parts of whole x rows: per split direction, 2 / extent of the part in it
+// (brick faces and part boundaries alike), none in a direction the brick
+// spans whole
+static int check_part_faces() {
+    const int L[4] = {48, 48, 48, 96};
+    int fails = 0;
+    struct Case { int a, b, c, w, want; };
+    const Case cs[] = {
+        {48, 2, 4, 384, 240 * 3 / 2},  // y 1 + z 1/2
+        {48, 2, 8, 192, 240 * 2},      // parts 48x2x2: y 1 + z 1
+        {48, 4, 4, 192, 240 * 5 / 2},  // parts 48x4x1: y 1/2 + z 2
+        {48, 1, 16, 192, 240 * 5 / 2}, // parts 48x1x4: y 2 + z 1/2
+        {48, 2, 8, 768, 240 * 5 / 4},  // whole brick: y 1 + z 1/4
+        {16, 4, 4, 256, 240 * 9 / 8},  // x split too: x 1/8 + y 1/2 + z 1/2
+    };
+    for (const Case &k : cs) {
+        const int got = wd::part_faces(L, k.a, k.b, k.c, k.w);
+        if (got != k.want) {
+            printf("part_faces %dx%dx%d w=%d: %d, want %d\n", k.a, k.b, k.c, k.w, got, k.want);
+            ++fails;
+        }
+    }
+    // the float64 part size rule: 192 where it divides, else up to 384
+    const int parts[][2] = {{768, 192}, {384, 192}, {192, 192}, {256, 256}, {320, 320},
+                            {512, 256}, {64, 64}, {1024, 256}};
+    for (const auto &q : parts)
+        if (wd::part_sites(q[0], WD_F64) != q[1]) {
+            printf("part_sites(%d) = %d, want %d\n", q[0], wd::part_sites(q[0], WD_F64), q[1]);
+            ++fails;
+        }
+    return fails;
+}
+
 int main() {
     int f = 0;
+    f += check_part_faces();
     f += check_choice(48, 48, 48, 96);
     f += check_choice(24, 24, 24, 48);
     f += check_choice(16, 16, 16, 32);
