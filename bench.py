@@ -27,6 +27,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -823,7 +824,12 @@ def pmc_summary(args):
            "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
                                 "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
            "kernels": {}}
-    grp = {"f64": 1, "f32": 2, "f16": 2}
+    # kernel names carry the hop scheduling group (a tuning constant) in the
+    # fourth template argument: match any
+    def named(rows, i, dag, red, xr, lf):
+        pat = re.compile(rf"k_dslash_tm<{i}, {dag}, {red}, \d+, false, {xr}, {lf}>")
+        return [r for r in rows if pat.search(r["name"])]
+
     kinds = []
     for i, prec in enumerate(("f64", "f32", "f16")):
         # the plain stencil (D, no reduction) and the CG's r-updating D^dag;
@@ -833,13 +839,11 @@ def pmc_summary(args):
             b, bx = BYTES_PER_SITE[prec], XR_BYTES_PER_SITE[prec]
             if link is not None:
                 b, bx = b - 576 + link, bx - 576 + link
-            kinds.append((prec, f"k_dslash_tm<{i}, false, false, {grp[prec]}, false, false, {lf}>",
-                          b))
-            kinds.append(("xr_" + prec,
-                          f"k_dslash_tm<{i}, true, true, {grp[prec]}, false, true, {lf}>", bx))
-    for key, tag, bps in kinds:
-        fr = [r for r in fetch if tag in r["name"]]
-        wr = [r for r in write if tag in r["name"]]
+            kinds.append((prec, (i, "false", "false", "false", lf), b))
+            kinds.append(("xr_" + prec, (i, "true", "true", "true", lf), bx))
+    for key, sig, bps in kinds:
+        fr = named(fetch, *sig)
+        wr = named(write, *sig)
         if not fr or not wr:
             continue
         # the 48^3 x 96 launches (the batched probe on 24^3 x 48 has another
@@ -862,9 +866,8 @@ def pmc_summary(args):
             "traffic_over_algorithmic": round(traffic / alg, 3),
             "traffic_bytes_per_site": round(traffic / V, 1)}
     # the batched FP32 stencil, 12 sources on 24^3 x 48: bytes per rhs-site
-    tag = "k_dslash_tm<1, false, false, 2, false, false, 1>"
-    fr = [r for r in fetch if tag in r["name"]]
-    wr = [r for r in write if tag in r["name"]]
+    fr = named(fetch, 1, "false", "false", "false", 1)
+    wr = named(write, 1, "false", "false", "false", 1)
     if fr and wr and fr[-1]["grid"] != fr[0]["grid"]:
         g12 = fr[-1]["grid"]
         fk = statistics.median(r["FETCH_SIZE"] for r in fr if r["grid"] == g12)
