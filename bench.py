@@ -136,7 +136,8 @@ def main():
         return valu_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
-                          "(the multi-GPU halo-exchange path is a design, not built)"}))
+                          "(no collective exchange is built; one GPU's share of a t-slab "
+                          "split is measured under extras.slab_share)"}))
         sys.exit(2)
     import numpy as np
     import torch
