@@ -174,6 +174,21 @@ static int check_part_faces() {
             printf("part_sites(%d) = %d, want %d\n", q[0], wd::part_sites(q[0], WD_F64), q[1]);
             ++fails;
         }
+    // the GPU tests' ragged case: 4x20x20x20 with 12 rhs marches chunks of
+    // 3 time slices, so the last chunk of a column has 2
+    {
+        wd::Geom g{};
+        g.L[0] = 4; g.L[1] = 20; g.L[2] = 20; g.L[3] = 20;
+        g.V = 4 * 20 * 20 * 20;
+        wd::choose_bricks(g);
+        for (int prec = 0; prec < 3; ++prec)
+            if (!wd::tm_eligible(g) ||
+                wd::tm_chunk_len(g, 12 * (g.bvol / wd::tm_wvol(g, prec)), 0) != 3) {
+                printf("4x20x20x20: chunk %d, want 3\n",
+                       wd::tm_chunk_len(g, 12 * (g.bvol / wd::tm_wvol(g, prec)), 0));
+                ++fails;
+            }
+    }
     return fails;
 }
 

@@ -133,6 +133,25 @@ def test_dslash_384_site_bricks(torch_dev, wd, monkeypatch, prec, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_dslash_ragged_last_chunk_twelve_rhs(torch_dev, wd, prec):
+    """4x20x20x20 with 12 rhs: the marching stencil takes chunks of 3 time
+    slices, so the last chunk of every column has 2 (20 = 6 x 3 + 2; the host
+    layout check pins this chunk length).  D and D^dag against the oracle
+    for every rhs."""
+    torch, dev = torch_dev
+    dims = (4, 20, 20, 20)
+    print(f"ragged last chunk, 12 rhs, prec={prec}", flush=True)
+    U = gauge(dims, 29, "exp")
+    psi = synth.gaussian_sources(dims, [30 + k for k in range(12)])
+    for dagger in (0, 1):
+        got = _apply(wd, torch, dev, dims, U, psi, 0.1245, prec, dagger, nrhs=12)
+        got = got.reshape(psi.shape)
+        op = wilson.apply_Ddag if dagger else wilson.apply_D
+        for k in range(12):
+            assert site_rel_err(got[k], op(U, psi[k], dims, 0.1245)) <= TOL[prec], (dagger, k)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_dslash_bricks_larger_than_a_workgroup(torch_dev, wd, monkeypatch, prec):
     """Bricks of 16x8x6 = 768 sites: every precision marches the brick slice
     in several parts (float64 four of 192, the float kernels three of 256),
