@@ -189,6 +189,21 @@ static int check_part_faces() {
                 ++fails;
             }
     }
+    // and the even-odd one: 8x20x20x20 with 12 rhs, marching halves (float64
+    // and float32) in chunks of 3
+    {
+        wd::Geom g{};
+        g.L[0] = 8; g.L[1] = 20; g.L[2] = 20; g.L[3] = 20;
+        g.V = 8 * 20 * 20 * 20;
+        wd::choose_bricks(g);
+        for (int prec = 0; prec < 2; ++prec) {
+            const int w = wd::eo_wvol(g, prec);
+            if (!w || wd::tm_chunk_len(g, 12 * (g.bvol / 2 / w), 0) != 3) {
+                printf("8x20x20x20 even-odd: w %d, want a chunk of 3\n", w);
+                ++fails;
+            }
+        }
+    }
     return fails;
 }
 

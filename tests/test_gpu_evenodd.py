@@ -60,6 +60,21 @@ def test_schur_operator_parity(env, dims, prec, dagger):
     _check_schur(got, U, psi, dims, 0.1245, prec, dagger)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_schur_ragged_last_chunk_twelve_rhs(env, prec):
+    """8x20x20x20 with 12 rhs: the marching half-field stencil takes chunks of
+    3 time slices, the last one 2 (the host layout check pins this).  M and
+    M^dag against the oracle for every rhs."""
+    dims = (8, 20, 20, 20)
+    print(f"schur ragged last chunk, 12 rhs, prec={prec}", flush=True)
+    U = gauge(dims, 87)
+    psi = synth.gaussian_sources(dims, [88 + k for k in range(12)])
+    for dagger in (0, 1):
+        got = _schur(env, dims, U, psi, 0.1245, prec, dagger, nrhs=12).reshape(psi.shape)
+        for k in range(12):
+            _check_schur(got[k], U, psi[k], dims, 0.1245, prec, dagger)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f16"])
 def test_schur_multi_rhs_and_384_site_bricks(env, monkeypatch, prec):
     monkeypatch.setenv("WD_BRICK", "8,8,6")
