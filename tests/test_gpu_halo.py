@@ -91,6 +91,22 @@ def test_slabs_multi_rhs(env):
         assert site_rel_err(got[k], wilson.apply_D(U, psis[k], dims, 0.1245)) <= 1e-13
 
 
+def test_slabs_twelve_rhs_ragged_chunks(env):
+    """Two 4x20x20x20 slabs of 4x20x20x40 with 12 rhs: each slab marches
+    chunks of 3 time slices, the last one 2, so the chunk holding the slab's
+    last slice (and the next slab's face) is the ragged one.  Against the
+    global oracle stencil, every rhs."""
+    dims = (4, 20, 20, 40)
+    print("halo 12 rhs ragged chunks", flush=True)
+    U = gauge(dims, 117)
+    psis = synth.gaussian_sources(dims, [130 + k for k in range(12)])
+    for dagger in (False, True):
+        got = _slabs(env, dims, U, psis, 2, 0.1245, dagger)
+        op = wilson.apply_Ddag if dagger else wilson.apply_D
+        for k in range(12):
+            assert site_rel_err(got[k], op(U, psis[k], dims, 0.1245)) <= 1e-13, (dagger, k)
+
+
 @pytest.mark.parametrize("links12", ["1", "0"])
 def test_single_slab_equals_plain_stencil_bitwise(env, monkeypatch, links12):
     """One slab receiving its own faces is the whole (antiperiodic) lattice:
