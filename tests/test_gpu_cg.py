@@ -135,16 +135,18 @@ def test_multi_rhs_column_equals_single_bitwise(env, dims, prec):
         assert info[k]["reliable_updates"] == info1[0]["reliable_updates"]
 
 
-def test_twelve_rhs_ragged_chunks_residual(env):
-    """12 rhs on 4x20x20x20, where the marching stencil's chunks are 3 time
-    slices and the last one 2: batched FP64 CG; every rhs meets the true
-    normal residual, and its ||b - D x|| / ||b|| recomputed by the oracle
-    agrees with the reported one."""
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_twelve_rhs_ragged_chunks_residual(env, prec):
+    """12 rhs on 4x20x20x20, where the marching stencils' chunks are 3 time
+    slices and the last one 2: batched CG (FP64, and mixed with FP64
+    reliable updates); every rhs meets the true normal residual, and its
+    ||b - D x|| / ||b|| recomputed by the oracle agrees with the reported
+    one."""
     dims = (4, 20, 20, 20)
-    print("cg 12 rhs ragged chunks", flush=True)
+    print(f"cg 12 rhs ragged chunks prec={prec}", flush=True)
     U = gauge(dims, 31)
     B = synth.gaussian_sources(dims, [40 + k for k in range(12)])
-    rc, info, X = _solve(env, dims, U, B, 0.124, tol=1e-10, nrhs=12)
+    rc, info, X = _solve(env, dims, U, B, 0.124, tol=1e-10, prec=prec, nrhs=12)
     assert rc == 0, info
     for k in range(12):
         assert info[k]["true_rel_resid"] <= 1e-10
