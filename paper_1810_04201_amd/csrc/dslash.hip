@@ -25,8 +25,9 @@
 #ifndef WD_XCD_REMAP
 #define WD_XCD_REMAP 1
 #endif
-// hops per scheduling group (see k_dslash): float64 groups of 3 measured
-// 1-2% faster than 1, 2 or 6 with two marching workgroups per CU
+// hops per scheduling group (see k_dslash): with two marching workgroups
+// per CU, float64 groups of 3 measured 1-2% faster than 1 (2 and 6 within
+// 0.3% of 3)
 #ifndef WD_GROUP_F64
 #define WD_GROUP_F64 3
 #endif
@@ -347,8 +348,8 @@ __device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
 }
 
 // Time-marching stencil.  One workgroup per brick column, chunk of time
-// slices, part of the brick slice (all of it, or a contiguous half or
-// quarter) and rhs, one lane per site.  The workgroup steps through its
+// slices, part of the brick slice (all of it, or one of several contiguous
+// runs of whole tiles) and rhs, one lane per site.  The workgroup steps through its
 // slices together with two LDS images of its part:
 //  - at the start of step t the next slice t+1 is copied from memory into
 //    the spare image, while the x/y/z hops of slice t read their neighbours
@@ -360,10 +361,10 @@ __device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
 //  - the backward t hop U_t(x, t-1)^dag (1 -+ gamma_t) psi(x, t-1) is carried
 //    from the previous step in registers.
 // The hops are summed in the order of the one-lane-per-site kernel.
-// Logical blocks are ordered chunk, column, rhs (rhs fastest), so each XCD's
-// contiguous run covers one band of time slices of many neighbouring columns
-// (their shared brick faces stay in its L2), and the workgroups of all rhs
-// of a column run side by side and read its links from L2 after the first.
+// Logical blocks are ordered chunk, column, part, rhs (rhs fastest), so each
+// XCD's contiguous run covers one band of time slices of many neighbouring
+// columns, and the workgroups of all rhs of a column part run side by side
+// and read its links from L2 after the first.
 // The fused reduction writes one partial per (column, slice, part, rhs), so
 // its summation order does not depend on the chunk length or on nrhs.
 // HALO: the lattice is one t-slab of a larger one; the t hops across its
