@@ -25,3 +25,15 @@ def gauge(dims, seed, kind="exp"):
 
 def vol(dims):
     return int(np.prod(dims))
+
+
+def assert_same_count_parity(x, xo_n, bound=1e-9):
+    """A float64 GPU solution against the oracle's iterate after the same
+    number of CG steps: relative 2-norm and largest element difference (as a
+    fraction of the largest element) both within `bound`."""
+    a = np.asarray(x).ravel()
+    b = np.asarray(xo_n).ravel()
+    r = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    assert r <= bound and e <= bound, (r, e)
+    return r, e

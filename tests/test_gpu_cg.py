@@ -1,7 +1,9 @@
 """Parity of the HIP CG solve (wd_cg_solve) with the CPU oracle.
 
-FP64 CG: solution within 1e-9 of the oracle's CGNR (same tolerance) and
-iteration count within +-1; the true normal residual meets the tolerance.
+FP64 CG: iteration count within +-1 of the oracle's CGNR at the same
+tolerance, the true normal residual meets the tolerance, and the solution is
+within 1e-9 (relative 2-norm and largest element) of the oracle's iterate
+after the same number of CG steps.
 Mixed precision (FP32 / FP16 inner, FP64 reliable updates) and 12-rhs
 batches: FP64 true residual <= tol and each solution within the bound that
 the problem's condition number allows, against the oracle.
@@ -11,7 +13,7 @@ import pytest
 
 import synth
 from oracle import cg, dense, wilson
-from gpu_util import gauge, rel, vol
+from gpu_util import assert_same_count_parity, gauge, rel, vol
 
 pytestmark = pytest.mark.gpu
 
@@ -58,10 +60,11 @@ def test_fp64_cg_matches_oracle(env, dims, seed, kind, kappa, src):
     _, dev, wd = env
     assert rc == wd.WD_OK, info
     xo, it, oinfo = _oracle(dims, U, b, kappa, 1e-10)
-    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
     assert abs(info[0]["iters"] - it) <= 1, (info[0]["iters"], it)
     assert info[0]["true_rel_resid"] <= 1e-10
-    assert rel(x, xo) <= max(1e-9, 2e-10 * cond), (rel(x, xo), cond)
+    xo_n, itn, _ = _oracle_n(dims, U, b, kappa, info[0]["iters"])
+    assert itn == info[0]["iters"]
+    assert_same_count_parity(x, xo_n)
     # the reported ||b - D x|| / ||b|| agrees with the oracle's own operator
     r = b - wilson.apply_D(U, x, dims, kappa)
     rD = np.linalg.norm(r) / np.linalg.norm(b)
@@ -106,13 +109,13 @@ def test_multi_rhs_12_point_sources(env, prec):
     for k in range(12):
         assert info[k]["status"] == 0
         assert info[k]["true_rel_resid"] <= 1e-10
-        xo, it, oinfo = _oracle(dims, U, B[k], 0.124, 1e-12)
-        cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
-        assert rel(X[k], xo) <= max(1e-9, 2e-10 * cond)
         if prec == "f64":
-            assert abs(info[k]["iters"] - cg.cgnr(
-                lambda v: wilson.apply_D(U, v, dims, 0.124),
-                lambda v: wilson.apply_Ddag(U, v, dims, 0.124), B[k], tol=1e-10)[1]) <= 1
+            assert abs(info[k]["iters"] - _oracle(dims, U, B[k], 0.124, 1e-10)[1]) <= 1
+            assert_same_count_parity(X[k], _oracle_n(dims, U, B[k], 0.124, info[k]["iters"])[0])
+        else:
+            xo, it, oinfo = _oracle(dims, U, B[k], 0.124, 1e-12)
+            cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
+            assert rel(X[k], xo) <= max(1e-9, 2e-10 * cond)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
@@ -166,6 +169,9 @@ def test_cg_384_site_bricks(env, monkeypatch, prec):
     b = synth.gaussian_spinor(dims, 24)
     rc, info, x = _solve(env, dims, U, b, 0.124, tol=1e-10, prec=prec)
     assert rc == 0 and info[0]["true_rel_resid"] <= 1e-10
+    if prec == "f64":
+        assert_same_count_parity(x, _oracle_n(dims, U, b, 0.124, info[0]["iters"])[0])
+        return
     xo, it, oinfo = _oracle(dims, U, b, 0.124, 1e-12)
     cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
     assert rel(x, xo) <= max(1e-9, 2e-10 * cond)
@@ -184,11 +190,15 @@ def test_cgne_form_matches_oracle(env, prec):
     assert info[0]["true_rel_resid"] <= 1e-10 and info[0]["rel_resid_D"] <= 1.1e-10
     D = lambda v: wilson.apply_D(U, v, dims, 0.124)  # noqa: E731
     Dd = lambda v: wilson.apply_Ddag(U, v, dims, 0.124)  # noqa: E731
+    if prec == "f64":
+        assert abs(info[0]["iters"] - cg.cgne(D, Dd, b, tol=1e-10)[1]) <= 1
+        xo_n, itn, _ = cg.cgne(D, Dd, b, tol=1e-30, max_iter=info[0]["iters"])
+        assert itn == info[0]["iters"]
+        assert_same_count_parity(x, xo_n)
+        return
     xo, it, oinfo = cg.cgne(D, Dd, b, tol=1e-12)
     cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
     assert rel(x, xo) <= max(1e-9, 2e-10 * cond)
-    if prec == "f64":
-        assert abs(info[0]["iters"] - cg.cgne(D, Dd, b, tol=1e-10)[1]) <= 1
 
 
 def test_plus_kappa_solve_matches_oracle(env):
@@ -210,9 +220,10 @@ def test_plus_kappa_solve_matches_oracle(env):
     D = lambda v: wilson.apply_D(U, v, dims, 0.124, hop_sign=+1)  # noqa: E731
     Dd = lambda v: wilson.apply_Ddag(U, v, dims, 0.124, hop_sign=+1)  # noqa: E731
     xo, it, oinfo = cg.cgnr(D, Dd, b, tol=1e-10)
-    cond = cg.lanczos_condition(oinfo["alphas"], oinfo["betas"])
-    assert rel(x, xo) <= max(1e-9, 2e-10 * cond)
     assert abs(info[0]["iters"] - it) <= 1
+    xo_n, itn, _ = cg.cgnr(D, Dd, b, tol=1e-30, max_iter=info[0]["iters"])
+    assert itn == info[0]["iters"]
+    assert_same_count_parity(x, xo_n)
 
 
 def test_deterministic_bitwise(env):
@@ -348,9 +359,12 @@ def test_fused_update_equals_separate_update(env, monkeypatch, prec, nrhs):
         assert inf_f[k]["true_rel_resid"] <= 1e-10 and inf_u[k]["true_rel_resid"] <= 1e-10
         if prec == "f64":
             assert abs(inf_f[k]["iters"] - inf_u[k]["iters"]) <= 1
-            assert rel(xf[k], xu[k]) <= 1e-9
-    assert rel(xf[0], xo) <= max(1e-9, 2e-10 * cond)
-    assert rel(xu[0], xo) <= max(1e-9, 2e-10 * cond)
+    if prec == "f64":
+        for xx, inf in ((xf, inf_f), (xu, inf_u)):
+            assert_same_count_parity(xx[0], _oracle_n(dims, U, B[0], kappa, inf[0]["iters"])[0])
+    else:
+        assert rel(xf[0], xo) <= max(1e-9, 2e-10 * cond)
+        assert rel(xu[0], xo) <= max(1e-9, 2e-10 * cond)
 
 
 @pytest.mark.parametrize("fuse", ["1", "0"])
@@ -413,3 +427,28 @@ def test_full_size_solves_residual_by_oracle_samples(env):
         assert est <= 1e-9
         assert 0.5 <= est / info[0]["rel_resid_D"] <= 2.0, (est, info[0]["rel_resid_D"])
     lat.close()
+
+
+def test_batched_point_sources_24x48_residual_by_oracle(env):
+    """The batched-sources workload at its own size: 24^3 x 48, kappa 0.124,
+    eps = 0.3 links seed 4, the 12 spin x colour point sources at the origin
+    in one call, FP32 inner solves with FP64 reliable updates (Sec. 2.3: the
+    same U with a new eta).  Every rhs meets the FP64 true normal residual;
+    for six of them (every spin and every colour) the oracle recomputes
+    ||b - D x|| / ||b|| over the whole lattice from the GPU's x, which must
+    agree with the reported value and stay below 1e-8."""
+    torch, dev, wd = env
+    dims = (24, 24, 24, 48)
+    print("12 point sources 24^3x48: generating links", flush=True)
+    U = gauge(dims, 4)
+    B = synth.spin_colour_point_sources(dims)
+    rc, info, X = _solve(env, dims, U, B, 0.124, tol=1e-10, prec="f32", nrhs=12)
+    assert rc == 0, info
+    for k in range(12):
+        assert info[k]["status"] == 0 and info[k]["true_rel_resid"] <= 1e-10, (k, info[k])
+    for k in (0, 2, 4, 7, 9, 11):
+        print(f"  oracle residual of rhs {k}", flush=True)
+        r = B[k] - wilson.apply_D(U, X[k], dims, 0.124)
+        rD = np.linalg.norm(r) / np.linalg.norm(B[k])
+        assert rD <= 1e-8, (k, rD)
+        assert abs(rD - info[k]["rel_resid_D"]) <= 1e-3 * rD + 1e-15, (k, rD, info[k])

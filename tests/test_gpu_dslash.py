@@ -397,3 +397,30 @@ def test_f64_links_not_special_unitary_stay_18_real(torch_dev, wd):
         torch.cuda.synchronize()
         assert site_rel_err(od.cpu().numpy(), wilson.apply_Ddag(Ux, psi, dims, 0.1245)) <= 1e-13
     lat.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (8, 8, 8, 8)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_wd_apply_D_and_Ddag_by_name(torch_dev, wd, dims, prec):
+    """The two operator entry points of the boundary, called by their own C
+    names through ctypes (wd.lib.wd_apply_D / wd.lib.wd_apply_Ddag), against
+    the oracle's D and D^dag of Eq. (1) site by site; (8,8,8,8) runs the
+    marching stencil, (4,6,8,10) the one-lane-per-site one."""
+    import ctypes
+    torch, dev = torch_dev
+    U = gauge(dims, 41)
+    psi = synth.gaussian_spinor(dims, 42)
+    k = 0.1245
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(U).to(dev))
+    pd = torch.from_numpy(psi).to(dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for name, ref in (("wd_apply_D", wilson.apply_D), ("wd_apply_Ddag", wilson.apply_Ddag)):
+        od = torch.full_like(pd, float("nan"))
+        rc = getattr(wd.lib, name)(lat.handle, ctypes.c_double(k), wd.PREC[prec],
+                                   ctypes.c_void_p(pd.data_ptr()),
+                                   ctypes.c_void_p(od.data_ptr()), stream)
+        assert rc == wd.WD_OK, wd.last_error()
+        torch.cuda.synchronize()
+        assert site_rel_err(od.cpu().numpy(), ref(U, psi, dims, k)) <= TOL[prec], name
+    lat.close()

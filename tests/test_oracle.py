@@ -363,3 +363,49 @@ def test_paper_table4_from_formula():
         perf = V * f * nu / (V * delta + tau) / 1e9
         assert abs(perf - printed) / printed < 5e-3, name
     assert (9 * 24 + 8 * 18) * 8 == 2880
+
+
+# ------------------------------------------------------------------ condition estimate
+#
+# cg.lanczos_condition turns CG's step lengths into the Lanczos tridiagonal of
+# D^dag D (Sec. 2.2 iteration; the Ritz values of that matrix interlace the
+# spectrum).  Its largest-to-smallest Ritz ratio can therefore never exceed
+# the exact condition number, and once CG has converged it must be close to
+# it.  Two independent pins: the eigenvalues of the dense D^dag D on 2^4-type
+# lattices, and the free-field closed form a(p)^2 + |b(p)|^2 at 4^4.
+
+@pytest.mark.parametrize("dims,seed,kappa,kind", [((2, 2, 2, 2), 1, 0.12, synth.HAAR),
+                                                  ((2, 2, 2, 4), 3, 0.15, synth.HAAR),
+                                                  ((2, 2, 2, 2), 5, 0.124, synth.EXP)])
+def test_lanczos_condition_vs_dense_eigenvalues(dims, seed, kappa, kind):
+    U = synth.gauge(dims, seed, kind, 0.3)
+    M = dense.dense_D(U, dims, kappa)
+    ev = np.linalg.eigvalsh(M.conj().T @ M)
+    exact = ev[-1] / ev[0]
+    b = synth.gaussian_spinor(dims, seed + 10)
+    D = lambda v: wilson.apply_D(U, v, dims, kappa)  # noqa: E731
+    Dd = lambda v: wilson.apply_Ddag(U, v, dims, kappa)  # noqa: E731
+    _, _, info = cg.cgnr(D, Dd, b, tol=1e-10)
+    est = cg.lanczos_condition(info["alphas"], info["betas"])
+    assert est <= exact * (1 + 1e-9), (est, exact)
+    assert est >= 0.99 * exact, (est, exact)
+
+
+def test_lanczos_condition_free_field_closed_form():
+    """U = 1 on 4^4 (antiperiodic t): D^dag D is a(p)^2 + |b(p)|^2 times the
+    identity on each momentum, so cond = max / min over the allowed momenta."""
+    dims = (4, 4, 4, 4)
+    kappa = 0.12
+    lam = np.array([free.DdagD_eigenvalue(p, kappa) for p in free.momenta(dims)])
+    exact = lam.max() / lam.min()
+    U = synth.gauge_unit(dims)
+    b = synth.gaussian_spinor(dims, 77)
+    D = lambda v: wilson.apply_D(U, v, dims, kappa)  # noqa: E731
+    Dd = lambda v: wilson.apply_Ddag(U, v, dims, kappa)  # noqa: E731
+    _, it, info = cg.cgnr(D, Dd, b, tol=1e-10)
+    est = cg.lanczos_condition(info["alphas"], info["betas"])
+    assert est <= exact * (1 + 1e-9), (est, exact)
+    assert est >= 0.999 * exact, (est, exact)
+    # CG on a scalar-per-momentum operator ends within the number of its
+    # distinct eigenvalues (one more step in floating point)
+    assert it <= len(np.unique(np.round(lam, 12))) + 1

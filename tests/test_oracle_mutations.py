@@ -102,3 +102,41 @@ def test_cgne_swapped_operators_caught(monkeypatch):
     monkeypatch.setattr(ocg, "cgne", lambda mv, mvd, b, **kw: real(mvd, mv, b, **kw))
     with pytest.raises(AssertionError):
         T.test_cgne_vs_lapack_tiny((2, 2, 2, 4), 3, 0.124)
+
+
+def _lanczos(mutation):
+    """A copy of the Lanczos condition estimate with one planted mistake."""
+
+    def lanczos_condition(alphas, betas):
+        n = len(alphas)
+        T = np.zeros((n, n))
+        for k in range(n):
+            if mutation == "diag_same_index":
+                T[k, k] = 1.0 / alphas[k] + (betas[k] / alphas[k] if k > 0 else 0.0)
+            else:
+                T[k, k] = 1.0 / alphas[k] + (betas[k - 1] / alphas[k - 1] if k > 0 else 0.0)
+            if k + 1 < n:
+                off = betas[k] if mutation == "no_sqrt" else np.sqrt(betas[k])
+                T[k, k + 1] = T[k + 1, k] = off / alphas[k]
+        ev = np.linalg.eigvalsh(T)
+        return float(ev[-1] / ev[0])
+
+    return lanczos_condition
+
+
+LANCZOS_PINS = [
+    lambda: T.test_lanczos_condition_vs_dense_eigenvalues((2, 2, 2, 2), 1, 0.12, T.synth.HAAR),
+    lambda: T.test_lanczos_condition_free_field_closed_form(),
+]
+
+
+@pytest.mark.parametrize("mutation", ["none", "no_sqrt", "diag_same_index"])
+def test_lanczos_mutation_caught(monkeypatch, mutation):
+    monkeypatch.setattr(ocg, "lanczos_condition", _lanczos(mutation))
+    failed = False
+    for pin in LANCZOS_PINS:
+        try:
+            pin()
+        except AssertionError:
+            failed = True
+    assert failed == (mutation != "none")
