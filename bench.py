@@ -153,7 +153,7 @@ def main():
     kappa = args.kappa
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
-    copy_gbs = copy_bandwidth(torch)
+    copy_gbs = copy_bandwidth(torch, wd)
 
     t0 = time.time()
     Uh = torch.empty((V, 4, 3, 3, 2), dtype=torch.float64, pin_memory=True)
@@ -182,32 +182,45 @@ def main():
     for w in range(args.warmup):
         step()
         log(f"warmup {w} done")
-    wd.wd_timing_reset()
-    wd.wd_timing_enable(True)
+    # the timed region: K steps on the default solver path (chunks of CG
+    # iterations replayed from HIP graphs, no event timing)
     torch.cuda.synchronize()
     t_start = time.time()
-    apps = {k: 0 for k in ("f64", "f32", "f16", "xr_f64", "xr_f32", "xr_f16")}
     per_step = []
     for k in range(args.steps):
         ts = time.time()
         i1, i2 = step()
         torch.cuda.synchronize()
         per_step.append({"t": time.time() - ts, "fp64": i1, "mixed": i2})
-        for info, p in ((i1, "f64"), (i2, args.mixed)):
-            for key, n in applications(info, p).items():
-                apps[key] += n
         log(f"step {k}: {per_step[-1]['t']:.2f}s fp64 {i1['seconds']:.2f}s/{i1['iters']} it, "
             f"{args.mixed} {i2['seconds']:.2f}s/{i2['iters']} it/{i2['reliable_updates']} upd")
     torch.cuda.synchronize()
     elapsed = time.time() - t_start
+    # kernel timing: the same step again (up to 3 times) with HIP events
+    # recorded on the launch stream around every stencil launch (the solver
+    # launches eagerly while events are recorded)
+    n_timed = min(args.steps, 3)
+    apps = {k: 0 for k in ("f64", "f32", "f16", "xr_f64", "xr_f32", "xr_f16")}
+    wd.wd_timing_reset()
+    wd.wd_timing_enable(True)
+    for k in range(n_timed):
+        i1, i2 = step()
+        for info, p in ((i1, "f64"), (i2, args.mixed)):
+            for key, n in applications(info, p).items():
+                apps[key] += n
+    torch.cuda.synchronize()
     wd.wd_timing_enable(False)
+    log(f"kernel timing: {n_timed} instrumented steps")
     ms = {k: wd.wd_timing_read("dslash_" + k)[0] for k in apps}
     BYTES_PER_SITE["f64"], XR_BYTES_PER_SITE["f64"] = f64_bytes(lat)
     f64_link_reals = lat.links_info()[0]
     msl, cntl = wd.wd_timing_read("dslash_" + args.mixed)
 
-    total_apps = sum(apps.values())
-    value = total_apps * V * FLOP_PER_SITE / elapsed / 1e9
+    # the headline: the FP64 stencil's GFLOP/s (1320 flop per site) over its
+    # average launch time inside the FP64 CG (t = D p, and D^dag b, the
+    # reliable updates and the final residual)
+    f64_ms = ms["f64"] / apps["f64"]
+    value = V * FLOP_PER_SITE / (f64_ms * 1e-3) / 1e9
     t_fp64 = statistics.median(s["fp64"]["seconds"] for s in per_step)
     t_mix = statistics.median(s["mixed"]["seconds"] for s in per_step)
     s0 = per_step[-1]
@@ -215,7 +228,7 @@ def main():
 
     def roof(key, what):
         """HBM roofline of one stencil kernel: average over its working
-        launches in the timed steps."""
+        launches in the instrumented steps."""
         avg_ms = ms[key] / apps[key]
         prec = key[-3:]
         bps = XR_BYTES_PER_SITE[prec] if key.startswith("xr_") else BYTES_PER_SITE[prec]
@@ -235,8 +248,8 @@ def main():
             "launches": apps[key],
             "bytes_per_site": bps,
             "sites_per_launch": V,
-            "copy_GBps": round(copy_gbs, 1),
-            "frac_of_copy": round(achieved / copy_gbs, 4),
+            "copy_GBps": round(copy_gbs["probe"], 1),
+            "frac_of_copy": round(achieved / copy_gbs["probe"], 4),
         }
 
     plain = roof("f64", f"dslash_f64 (k_dslash_tm<F64>, time-marching stencil, "
@@ -260,18 +273,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"f64+{args.mixed}",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"Wilson-Dirac CGNR {'x'.join(map(str, dims))} kappa={kappa} "
-                        f"exp(i*0.3*H) SU(3) links seed 3, Gaussian source seed 103, "
-                        f"true rel. residual {args.tol}: FP64 CG + mixed {args.mixed.upper()}-12 CG",
+            "workload": f"FP64 Wilson-Dirac dslash (1320 flop/site, F64-{f64_link_reals} links) "
+                        f"inside CGNR on {'x'.join(map(str, dims))}, kappa={kappa}, "
+                        f"exp(i*0.3*H) SU(3) links seed 3, Gaussian source seed 103; one step = "
+                        f"gauge ingest + FP64 CG + mixed {args.mixed.upper()}-12 CG to a true "
+                        f"relative residual of {args.tol}",
             "lattice": "x".join(map(str, dims)),
             "kappa": kappa,
             "tol": args.tol,
             "parallelism": "single GPU",
         },
+        "value_source": (f"1320 flop x {V} sites over the average launch time of the FP64 "
+                         f"stencil (t = D p) measured with HIP events on its launch stream over "
+                         f"{apps['f64']} launches in {n_timed} instrumented steps"),
+        "dslash_f64": {"GFLOPs": round(value, 1), "avg_launch_ms": round(f64_ms, 4),
+                       "GBps_algorithmic": round(V * BYTES_PER_SITE["f64"] / f64_ms / 1e6, 1),
+                       "bytes_per_site": BYTES_PER_SITE["f64"], "launches": apps["f64"]},
         "cg": {
+            "timing": "median over the timed steps, default solver path (HIP graph replays)",
             "fp64_s": round(t_fp64, 3),
             "fp64_iters": s0["fp64"]["iters"],
             "fp64_true_rel_resid": s0["fp64"]["true_rel_resid"],
@@ -282,10 +304,12 @@ def main():
             "speedup_mixed_vs_fp64": round(t_fp64 / t_mix, 3),
         },
         "roofline": roofline,
+        "copy_ceiling": copy_gbs,
     }
     if cntl:
         ml = msl / apps[args.mixed]
         out["roofline_" + args.mixed] = {
+            "kernel": f"dslash_{args.mixed} (the mixed CG's inner stencil)",
             "avg_launch_ms": round(ml, 4),
             "achieved_GBps": round(V * BYTES_PER_SITE[args.mixed] / (ml * 1e-3) / 1e9, 1),
             "GFLOPs": round(V * FLOP_PER_SITE / (ml * 1e-3) / 1e9, 1),
@@ -302,6 +326,7 @@ def main():
         ex.update(other_mixed(args, lat, bd, kappa, stream, torch))
         ex["even_odd"] = even_odd(args, wd, lat, bd, kappa, stream, torch, V)
         lat.close()
+        ex["f16_links8"] = f16_links8(wd, torch, dims, Ud, bd, V, kappa, args.tol, stream)
         del Ud
         torch.cuda.empty_cache()
         ex["slab_share"] = slab_share(np, torch, synth, wd)
@@ -314,32 +339,43 @@ def main():
     if not args.no_cpu:
         it16 = (out.get("extras", {}).get("small_configs", {}).get("16x16x16x32", {})
                 .get("cg_f64_iters"))
-        out["cpu_baseline"] = cpu_baseline(np, it16)
+        out["cpu_baseline"] = cpu_baseline(np, it16, s0["fp64"]["iters"] if full else None)
     print(json.dumps(out))
 
 
-def copy_bandwidth(torch):
-    """Device-to-device copy of 2 GiB (read + write bytes over time, median
-    of 5): the practical streaming ceiling next to the 8 TB/s peak."""
+def copy_bandwidth(torch, wd):
+    """Streaming ceilings, median of 5 (read + write bytes over the kernel
+    time, HIP events): the library's streaming copy probe (wd_stream_copy,
+    16-byte non-temporal loads and stores) on 2 GiB, the reference for the
+    stencils' rates next to the 8 TB/s peak; torch's device copy beside it."""
     n = 256 * 1024 * 1024
     a = torch.ones(n, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
-    for _ in range(2):
-        b.copy_(a)
-    ts = []
-    for _ in range(5):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1))
+
+    def med(fn):
+        for _ in range(2):
+            fn()
+        ts = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return 2 * n * 8 / statistics.median(ts) / 1e6
+
+    res = {"probe": med(lambda: wd.wd_stream_copy(a, b)), "torch_copy": med(lambda: b.copy_(a)),
+           "bytes": 2 * n * 8, "peak": HBM_PEAK_GBS}
+    assert torch.equal(a, b)
+    res["probe_frac_of_peak"] = round(res["probe"] / HBM_PEAK_GBS, 4)
+    res["probe"] = round(res["probe"], 1)
+    res["torch_copy"] = round(res["torch_copy"], 1)
     del a, b
     torch.cuda.empty_cache()
-    gbs = 2 * n * 8 / statistics.median(ts) / 1e6
-    log(f"copy: {gbs:.0f} GB/s")
-    return gbs
+    log(f"copy: {res}")
+    return res
 
 
 def slab_share(np, torch, synth, wd):
@@ -483,6 +519,46 @@ def stencil_alone(wd, torch, lat, bd, V, kappa, stream):
         fa.close()
         fb.close()
     log(f"stencil alone: {res}")
+    return res
+
+
+def f16_links8(wd, torch, dims, Ud, bd, V, kappa, tol, stream):
+    """The same system on a lattice whose binary16 links are stored as 8
+    reals (16 bytes per link, WD_F16_LINKS_8): the binary16 stencil alone
+    (algorithmic bytes 52 + 64 + 52 per site) and the mixed FP16-8 CG."""
+    lat = wd.Lattice(dims, f16_links8=True)
+    with torch.cuda.stream(stream):
+        lat.set_gauge(Ud, stream=stream)
+        fa, fb = wd.Field(lat, "f16"), wd.Field(lat, "f16")
+        fa.load(bd, stream=stream)
+        for _ in range(3):
+            wd.wd_dslash(lat, kappa, 0, fa, fb, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(20):
+            wd.wd_dslash(lat, kappa, i & 1, fa, fb, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    fa.close()
+    fb.close()
+    x = torch.zeros_like(bd)
+    with torch.cuda.stream(stream):
+        lat.solve(bd, x, kappa, tol=tol, prec="f16", stream=stream)  # warm
+        x.zero_()
+        rc, info = lat.solve(bd, x, kappa, tol=tol, prec="f16", stream=stream)
+    torch.cuda.synchronize()
+    bps = 52 + 64 + 52
+    res = {"dslash_f16_8_ms": round(ms, 4),
+           "dslash_f16_8_GFLOPs": round(V * FLOP_PER_SITE / ms / 1e6, 1),
+           "dslash_f16_8_GBps_algorithmic": round(V * bps / ms / 1e6, 1),
+           "bytes_per_site": bps,
+           "mixed_f16_8_s": round(info[0]["seconds"], 3), "mixed_f16_8_iters": info[0]["iters"],
+           "mixed_f16_8_reliable_updates": info[0]["reliable_updates"],
+           "mixed_f16_8_true_rel_resid": info[0]["true_rel_resid"], "rc": rc}
+    lat.close()
+    log(f"f16 links8: {res}")
     return res
 
 
@@ -684,37 +760,68 @@ def serving(np, torch, synth, wd, n_requests):
     return res
 
 
-def cpu_baseline(np, iters_16=None):
-    """The CPU oracle's stencil (NumPy, complex128) on 16^3 x 32, median of 3;
-    its CG on the 4^4 configuration to solution; and 3 CG iterations on
-    16^3 x 32, extrapolated to the iteration count the GPU solve took."""
+def cpu_baseline(np, iters_16=None, iters_48=None):
+    """The CPU oracle (NumPy, complex128, one thread), timed on this host.
+
+    The headline `value` is the oracle on a bounded sample of the benchmark
+    workload itself: one D^dag D application (apply_D then apply_Ddag) on a
+    48^3 x 6 t-slab of the 48^3 x 96 configuration (links seed 3 for t = 0..5,
+    the Gaussian source seed 103 on those sites; the slab's t ends wrap, so
+    this is a timing sample, not a result), in GFLOP/s at 1320 flop per site
+    and application.  From it, the FP64 CG on 48^3 x 96 is extrapolated: the
+    sampled D^dag D time per site x V x the GPU solve's iteration count
+    (vector updates not counted), labelled as extrapolated.  Also: the
+    oracle's stencil on 16^3 x 32 (median of 5), its CG to solution on the
+    4^4 configuration, and 3 CG iterations on 16^3 x 32 extrapolated to the
+    GPU's iteration count."""
     import synth
-    from oracle import wilson
+    from oracle import cg, wilson
+    full = (48, 48, 48, 96)
+    ts_ = 6
+    slab = (48, 48, 48, ts_)
+    vs = 48 ** 3 * ts_
+    Us = synth.gauge(full, 3, synth.EXP, 0.3, t0=0, t1=ts_)
+    ps = synth.gaussian_spinor(full, 103, s0=0, s1=vs)
+    t = time.time()
+    y = wilson.apply_D(Us, ps, slab, 0.1245)
+    t_d = time.time() - t
+    t = time.time()
+    wilson.apply_Ddag(Us, y, slab, 0.1245)
+    t_dd = time.time() - t
+    del Us, ps, y
+    gflops = 2 * vs * FLOP_PER_SITE / (t_d + t_dd) / 1e9
+    out = {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+           "sample": (f"oracle apply_D + apply_Ddag (NumPy einsum stencil, complex128) on a "
+                      f"48^3x{ts_} t-slab of the 48^3x96 workload: {t_d:.2f}s + {t_dd:.2f}s; "
+                      f"1 thread used (einsum is single-threaded), {os.cpu_count()} cores "
+                      f"present"),
+           "DdagD_48x48x48x96_s_per_site": (t_d + t_dd) / vs}
+    if iters_48:
+        out["cg_48x48x48x96_fp64_extrapolated_s"] = round((t_d + t_dd) / vs * 48 ** 3 * 96 *
+                                                          iters_48, 1)
+        out["cg_48x48x48x96_note"] = (f"extrapolated: the sampled D^dag D time per site x "
+                                      f"{48 ** 3 * 96} sites x the GPU solve's {iters_48} "
+                                      f"iterations (vector updates not counted)")
     dims = (16, 16, 16, 32)
     V = int(np.prod(dims))
     U = synth.gauge(dims, 2, synth.EXP, 0.3)
     psi = synth.gaussian_spinor(dims, 102)
     ts = []
-    for _ in range(3):
+    for _ in range(5):
         t = time.time()
         wilson.apply_D(U, psi, dims, 0.124)
         ts.append(time.time() - t)
-    t = statistics.median(ts)
-    # time to solution of the oracle's CG on the 4^4 configuration
-    from oracle import cg
+    t16 = statistics.median(ts)
+    out["stencil_16x16x16x32_GFLOPs"] = round(V * FLOP_PER_SITE / t16 / 1e9, 3)
+    out["stencil_16x16x16x32_note"] = f"median of 5 runs of {t16:.3f}s"
     d4 = (4, 4, 4, 4)
     U4 = synth.gauge(d4, 1, synth.HAAR, 0.3)
     b4 = synth.point_source(d4)
     tc = time.time()
     _, it4, _ = cg.cgnr(lambda v: wilson.apply_D(U4, v, d4, 0.12),
                         lambda v: wilson.apply_Ddag(U4, v, d4, 0.12), b4, tol=1e-10)
-    tc = time.time() - tc
-    out = {"value": round(V * FLOP_PER_SITE / t / 1e9, 3), "unit": "GFLOP/s",
-           "cores": 1, "kind": "oracle",
-           "sample": f"oracle apply_D (NumPy einsum stencil, complex128) on 16^3x32, median of 3 "
-                     f"runs of {t:.2f}s; 1 thread used (einsum is single-threaded), "
-                     f"{os.cpu_count()} cores present",
-           "cg_4x4x4x4_s": round(tc, 4), "cg_4x4x4x4_iters": it4}
+    out["cg_4x4x4x4_s"] = round(time.time() - tc, 4)
+    out["cg_4x4x4x4_iters"] = it4
     if iters_16:
         b16 = synth.gaussian_spinor(dims, 102)
         t3 = time.time()
@@ -722,8 +829,9 @@ def cpu_baseline(np, iters_16=None):
                 lambda v: wilson.apply_Ddag(U, v, dims, 0.124), b16, tol=1e-30, max_iter=3)
         t3 = (time.time() - t3) / 3
         out["cg_16x16x16x32_extrapolated_s"] = round(t3 * iters_16, 1)
-        out["cg_16x16x16x32_note"] = (f"3 oracle CG iterations ({t3:.2f} s each, D^dag b "
-                                      f"included) times the GPU solve's {iters_16}")
+        out["cg_16x16x16x32_note"] = (f"extrapolated: 3 oracle CG iterations ({t3:.2f} s each, "
+                                      f"D^dag b included) times the GPU solve's {iters_16}")
+    log(f"cpu baseline: {out}")
     return out
 
 

@@ -75,8 +75,18 @@ enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 };
 /* Lattice flags.  WD_SIGN_PLUS_KAPPA selects the hopping sign as printed in
  * Eq. (1), D = 1 + kappa * (hops); the default is D = 1 - kappa * (hops).
  * On even lattices the two are related by D_+ = eps D_- eps with
- * eps(x) = (-1)^(x+y+z+t): same spectrum, solutions differ by eps. */
-enum { WD_BC_ANTIPERIODIC_T = 1u << 0, WD_SIGN_PLUS_KAPPA = 1u << 1 };
+ * eps(x) = (-1)^(x+y+z+t): same spectrum, solutions differ by eps.
+ * WD_F16_LINKS_8 stores this lattice's binary16 links (WD_F16 operators and
+ * inner solves) as 8 reals per link, 16 bytes, instead of 12 (24 bytes):
+ * the parametrisation of a link by 8 real numbers that Sec. 6.1 leaves for
+ * later work, in a form whose rebuilt entries stay within a few binary16
+ * rounding units (row 0 led by its largest entry, rows 1 and 2 in a pivoted
+ * frame orthogonal to it).  Links must be special unitary. */
+enum {
+    WD_BC_ANTIPERIODIC_T = 1u << 0,
+    WD_SIGN_PLUS_KAPPA = 1u << 1,
+    WD_F16_LINKS_8 = 1u << 2
+};
 
 /* Normal-equation forms of the CG solve (Sec. 2.2), optionally on the
  * even-odd Schur complement: with WD_SOLVE_EVEN_ODD or'ed in, CG runs on
@@ -91,9 +101,9 @@ enum {
 /* ---------------------------------------------------------------- lattice */
 
 /* Create a lattice of extents dims (each even, >= 2).  bc_flags:
- * WD_BC_ANTIPERIODIC_T for antiperiodic t (else periodic everywhere), and
+ * WD_BC_ANTIPERIODIC_T for antiperiodic t (else periodic everywhere),
  * WD_SIGN_PLUS_KAPPA for the +kappa hopping sign on every operator of this
- * lattice.
+ * lattice, and WD_F16_LINKS_8 for 8-real binary16 links.
  * *out receives an opaque handle owned by the caller; free it with
  * wd_destroy_lattice.  Allocates no device memory yet. */
 int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out);
@@ -262,38 +272,66 @@ typedef struct {
 int wd_cg_solve(wd_lattice *lat, const wd_solve_params *p, const double *b, double *x,
                 wd_solve_info *info, void *stream);
 
-/* ---------------------------------------------------------------- serving */
+/* ---------------------------------------------------------------- serving
+ * Sec. 2.3 poses the solver's workload as a stream of solves: the gauge
+ * field stays resident while new sources eta arrive (and now and then a new
+ * field with its own sources).  A server takes such a stream of CG requests
+ * (lattices of different sizes, kappa, precisions, 1..12 sources each) and
+ * solves them concurrently on one GPU (continuous batching): requests are
+ * admitted in arrival order as slots and HBM free up, iterate side by side on
+ * their own streams, and retire independently.  Each request's result is
+ * bitwise the same as the same wd_cg_solve alone. */
 
 typedef struct {
-    size_t hbm_budget_bytes; /* cap on solver workspace + gauge forms of live requests */
-    int32_t max_active;      /* requests iterating at once (<= 0: 8) */
-    int32_t chunk_iters;     /* CG iterations enqueued per request per scheduling turn (<= 0: auto) */
+    size_t hbm_budget_bytes; /* cap on what the server's work holds in HBM:
+                                workspaces of running requests, float64 links
+                                of lattices with running requests, and every
+                                derived gauge form (float32, binary16,
+                                even-odd halves) resident on a lattice the
+                                server has solved on */
+    int32_t max_active;      /* requests iterating at once (<= 0: 8); with
+                                caller streams it is n_streams */
+    int32_t chunk_iters;     /* CG iterations enqueued per request per
+                                scheduling turn (<= 0: chosen from the volume) */
+    int32_t n_streams;       /* 0: the server creates one non-blocking stream
+                                per slot; > 0 (at most 64): the slots run on
+                                the caller's streams[0..n_streams-1] */
+    void *const *streams;    /* hipStream_t values (e.g. torch streams), owned
+                                by the caller, valid until wd_server_destroy
+                                returns; never destroyed by the server */
 } wd_server_config;
 
 /* Start a server with its own scheduler thread and one HIP stream per active
  * slot.  Requests are admitted in arrival order while the HBM budget and the
  * slot count allow; admitted requests iterate concurrently on their streams
- * and retire independently (continuous batching). */
+ * and retire independently (continuous batching).  When a request does not
+ * fit the budget, the server first releases derived gauge forms of lattices
+ * that have no running requests (they are rebuilt, bit for bit, on next
+ * use; a caller using such a lattice directly while the server runs must
+ * expect that).  WD_ERR_ARG for a zero budget or an invalid stream list. */
 int wd_server_create(const wd_server_config *cfg, wd_server **out);
 
 /* Queue a solve (non-blocking).  Same arguments as wd_cg_solve; the lattice
  * must have its gauge set and must outlive the request, and b must already
  * hold the source on the device (the server reads it from its own stream,
  * unordered with the caller's streams).  *ticket identifies the request.
- * WD_ERR_NOMEM if the request alone exceeds the whole budget. */
+ * WD_ERR_NOMEM if the request alone (its workspace, the lattice's float64
+ * links and the forms it reads) exceeds the whole budget; WD_ERR_STATE once
+ * the server is being destroyed. */
 int wd_submit(wd_server *s, wd_lattice *lat, const wd_solve_params *p, const double *b,
               double *x, uint64_t *ticket);
 
 /* WD_PENDING while queued or running; otherwise the solve's return code, with
- * info (host, nrhs entries) filled in.  A finished ticket may be polled again
- * until wd_server_destroy. */
+ * info (host, nrhs entries) filled in.  The 4096 most recently finished
+ * tickets may be polled again; older ones report WD_ERR_NOTFOUND (the
+ * server's bookkeeping does not grow with the requests it has served). */
 int wd_poll(wd_server *s, uint64_t ticket, wd_solve_info *info);
 
 /* Completed solves per second since the server started, and the 50th/99th
  * percentile (nearest rank) of completion - submission latency, seconds. */
 int wd_server_stats(wd_server *s, double *solves_per_s, double *p50_s, double *p99_s);
 
-/* Peak bytes the server had admitted at once (workspace + gauge forms). */
+/* Peak bytes the server has charged against its budget at once. */
 int wd_server_peak_bytes(wd_server *s, size_t *bytes);
 
 /* Drain every queued and running request, then free the server. */
@@ -304,6 +342,14 @@ int wd_server_destroy(wd_server *s);
 /* Thread-local text of the last error on this thread (library-owned, valid
  * until the next call on this thread). */
 const char *wd_last_error(void);
+
+/* Streaming probe for measurement: dst = src, `bytes` (a multiple of 16;
+ * both device pointers 16-byte aligned, not overlapping) moved with 16-byte
+ * non-temporal loads and stores, the access pattern of the solver's vector
+ * kernels.  Its rate (bytes read plus bytes written over the kernel time) is
+ * the device's practical streaming ceiling, beside the published HBM peak,
+ * for comparing the stencils' rates.  Stream-ordered. */
+int wd_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * stencil launch.  wd_timing_read returns the summed milliseconds and launch

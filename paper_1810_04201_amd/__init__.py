@@ -39,6 +39,7 @@ WD_ERR_STATE = -8
 WD_F64, WD_F32, WD_F16 = 0, 1, 2
 WD_BC_ANTIPERIODIC_T = 1
 WD_SIGN_PLUS_KAPPA = 2
+WD_F16_LINKS_8 = 4
 WD_FORM_CGNR, WD_FORM_CGNE = 0, 1
 WD_SOLVE_EVEN_ODD = 1 << 8
 WD_HALO_FIRST, WD_HALO_LAST, WD_HALO_INTERIOR, WD_HALO_ENDS = 1, 2, 4, 8
@@ -76,7 +77,8 @@ class wd_solve_info(ctypes.Structure):
 
 class wd_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
-                ("chunk_iters", ctypes.c_int32)]
+                ("chunk_iters", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("streams", ctypes.POINTER(ctypes.c_void_p))]
 
 
 _vp = ctypes.c_void_p
@@ -110,6 +112,7 @@ _SIGS = {
                         ctypes.POINTER(ctypes.c_double)],
     "wd_server_peak_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "wd_server_destroy": [_vp],
+    "wd_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "wd_last_error": [],
     "wd_timing_enable": [_i32],
     "wd_timing_reset": [],
@@ -188,10 +191,12 @@ def _dptr(t, numel=None, name="tensor"):
 
 # ------------------------------------------------------------------ C names
 
-def wd_create_lattice(dims, antiperiodic_t: bool = True, plus_kappa: bool = False):
+def wd_create_lattice(dims, antiperiodic_t: bool = True, plus_kappa: bool = False,
+                      f16_links8: bool = False):
     d = (ctypes.c_int32 * 4)(*[int(v) for v in dims])
     h = _vp()
-    flags = (WD_BC_ANTIPERIODIC_T if antiperiodic_t else 0) | (WD_SIGN_PLUS_KAPPA if plus_kappa else 0)
+    flags = ((WD_BC_ANTIPERIODIC_T if antiperiodic_t else 0) |
+             (WD_SIGN_PLUS_KAPPA if plus_kappa else 0) | (WD_F16_LINKS_8 if f16_links8 else 0))
     _check(lib.wd_create_lattice(d, flags, ctypes.byref(h)))
     return h
 
@@ -275,6 +280,18 @@ def wd_cg_solve(h, params: wd_solve_params, b, x, volume, stream=None):
     return rc, [i.as_dict() for i in infos]
 
 
+def wd_stream_copy(src, dst, stream=None):
+    """dst = src through the library's streaming probe kernel (any dtype;
+    contiguous device tensors of the same byte size, a multiple of 16)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst sizes differ")
+    for t in (src, dst):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("src and dst must be contiguous device tensors")
+    _check(lib.wd_stream_copy(_vp(src.data_ptr()), _vp(dst.data_ptr()), nb, _stream(stream)))
+
+
 def wd_timing_enable(on=True):
     _check(lib.wd_timing_enable(1 if on else 0))
 
@@ -295,10 +312,12 @@ def wd_timing_read(name: str):
 class Lattice:
     """Owns a wd_lattice handle: geometry plus resident packed gauge forms."""
 
-    def __init__(self, dims, antiperiodic_t: bool = True, plus_kappa: bool = False):
+    def __init__(self, dims, antiperiodic_t: bool = True, plus_kappa: bool = False,
+                 f16_links8: bool = False):
+        """f16_links8: binary16 links stored as 8 reals (WD_F16_LINKS_8)."""
         self.dims = tuple(int(v) for v in dims)
         self.volume = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
-        self.handle = wd_create_lattice(self.dims, antiperiodic_t, plus_kappa)
+        self.handle = wd_create_lattice(self.dims, antiperiodic_t, plus_kappa, f16_links8)
 
     def set_gauge(self, U, stream=None):
         wd_set_gauge(self.handle, U, self.volume, stream)
@@ -380,8 +399,18 @@ def wd_dslash(lattice: Lattice, kappa, dagger, fin: Field, fout: Field, stream=N
 class Server:
     """Continuous-batching solve server (wd_server_*)."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 8, chunk_iters: int = 0):
-        cfg = wd_server_config(int(hbm_budget_bytes), int(max_active), int(chunk_iters))
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 8, chunk_iters: int = 0,
+                 streams=None):
+        """streams: optional torch streams (or raw hipStream_t ints) for the
+        slots; the server then runs len(streams) requests at once on them."""
+        self._streams = list(streams or [])
+        arr = (ctypes.c_void_p * max(1, len(self._streams)))(
+            *[s if isinstance(s, int) else s.cuda_stream for s in self._streams])
+        self._stream_arr = arr
+        cfg = wd_server_config(int(hbm_budget_bytes), int(max_active), int(chunk_iters),
+                               len(self._streams),
+                               ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+                               if self._streams else None)
         h = _vp()
         _check(lib.wd_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

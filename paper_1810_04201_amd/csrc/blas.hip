@@ -79,7 +79,8 @@ __global__ void k_pack_gauge_f64(const double2 *__restrict__ canon, void *__rest
     }
 }
 
-// F64-18 -> 12-real forms (rows 0 and 1), rounded to nearest even
+// F64-18 -> the compressed forms: 12 reals (rows 0 and 1, rounded to nearest
+// even), or the 8-real binary16 form
 template <int PREC>
 __global__ void k_gauge_lo(const void *__restrict__ g, void *__restrict__ o, int V) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,6 +104,8 @@ void launch_gauge_lo(const void *g64, void *glo, int form, int V, hipStream_t s)
         hipLaunchKernelGGL(k_gauge_lo<WD_F32>, gr, bs, 0, s, g64, glo, V);
     else if (form == WD_F16)
         hipLaunchKernelGGL(k_gauge_lo<WD_F16>, gr, bs, 0, s, g64, glo, V);
+    else if (form == kLinkF16R8)
+        hipLaunchKernelGGL(k_gauge_lo<kLinkF16R8>, gr, bs, 0, s, g64, glo, V);
     else
         hipLaunchKernelGGL(k_gauge_lo<kLinkF64R12>, gr, bs, 0, s, g64, glo, V);
 }
@@ -170,6 +173,8 @@ void launch_gauge_split(const void *g64, void *half, int form, int p, const Geom
         hipLaunchKernelGGL(k_gauge_split<WD_F64>, gr, bs, 0, s, g64, half, p, geo);
     else if (prec == WD_F32)
         hipLaunchKernelGGL(k_gauge_split<WD_F32>, gr, bs, 0, s, g64, half, p, geo);
+    else if (form == kLinkF16R8)
+        hipLaunchKernelGGL(k_gauge_split<kLinkF16R8>, gr, bs, 0, s, g64, half, p, geo);
     else
         hipLaunchKernelGGL(k_gauge_split<WD_F16>, gr, bs, 0, s, g64, half, p, geo);
 }
@@ -375,7 +380,7 @@ void launch_accum_zero(FieldRef x, FieldRef xl, FieldRef p, Gate gate, hipStream
     else if (p.prec == WD_F32)
         hipLaunchKernelGGL((k_accum_zero<WD_F32, WD_F32>), gr, bs, 0, s, x, xl, p, gate);
     else
-        hipLaunchKernelGGL((k_accum_zero<WD_F32, WD_F16>), gr, bs, 0, s, x, xl, p, gate);
+        hipLaunchKernelGGL((k_accum_zero<kF16XrPrec, WD_F16>), gr, bs, 0, s, x, xl, p, gate);
 }
 
 // ------------------------------------------------------------------ CG updates
@@ -487,7 +492,7 @@ void launch_update_xp(FieldRef x, FieldRef p, FieldRef r, Gate gate, hipStream_t
     else if (p.prec == WD_F32)
         hipLaunchKernelGGL((k_update_xp<WD_F32, WD_F32>), gr, bs, 0, s, x, p, r, gate);
     else
-        hipLaunchKernelGGL((k_update_xp<WD_F32, WD_F16>), gr, bs, 0, s, x, p, r, gate);
+        hipLaunchKernelGGL((k_update_xp<kF16XrPrec, WD_F16>), gr, bs, 0, s, x, p, r, gate);
 }
 
 void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const RedArgs &red,
@@ -498,7 +503,7 @@ void launch_update_xr(FieldRef x, FieldRef r, FieldRef p, FieldRef Ap, const Red
     else if (p.prec == WD_F32)
         hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F32>), gr, bs, 0, s, x, r, p, Ap, red, gate);
     else
-        hipLaunchKernelGGL((k_update_xr<WD_F32, WD_F16>), gr, bs, 0, s, x, r, p, Ap, red, gate);
+        hipLaunchKernelGGL((k_update_xr<kF16XrPrec, WD_F16>), gr, bs, 0, s, x, r, p, Ap, red, gate);
     launch_finalize(red, gr.x, GATE_ACTIVE, s);
 }
 
@@ -510,7 +515,7 @@ static void update_p_impl(FieldRef p, FieldRef r, Gate gate, hipStream_t s) {
     else if (p.prec == WD_F32)
         hipLaunchKernelGGL((k_update_p<WD_F32, WD_F32, RESTART>), gr, bs, 0, s, p, r, gate);
     else
-        hipLaunchKernelGGL((k_update_p<WD_F32, WD_F16, RESTART>), gr, bs, 0, s, p, r, gate);
+        hipLaunchKernelGGL((k_update_p<kF16XrPrec, WD_F16, RESTART>), gr, bs, 0, s, p, r, gate);
 }
 
 void launch_update_p(FieldRef p, FieldRef r, Gate gate, hipStream_t s) {

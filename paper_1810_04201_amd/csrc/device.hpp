@@ -76,6 +76,7 @@ __device__ __forceinline__ const char *tile_elem(const void *base, size_t tile_b
 
 // ------------------------------------------------------------------ spinors
 
+
 // the field of one right-hand side: entries are then site indices
 __device__ __forceinline__ FieldRef rhs_view(FieldRef f, int rhs) {
     f.data = (char *)f.data + (size_t)rhs * (size_t)(f.stride >> 6) * spinor_tile_bytes(f.prec);
@@ -145,6 +146,18 @@ struct Spinor<WD_F16> {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
                 v[4 * j + m] = {s * (float)q[2 * m], s * (float)q[2 * m + 1]};
+        }
+    }
+    // the stored halves (v / s, one complex per half pair) and the scale s
+    template <bool NT = false>
+    static __device__ __forceinline__ void load_raw(const FieldRef &f, int i, h2_t q[12],
+                                                    float &s) {
+        s = ldv<NT>(scale_ptr(f, i));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const h8_t v = ldv<NT>((const h8_t *)tile_elem(f.data, kTileBytes, i, j));
+#pragma unroll
+            for (int m = 0; m < 4; ++m) q[4 * j + m] = h2_t{v[2 * m], v[2 * m + 1]};
         }
     }
     template <bool NT = false>
@@ -262,6 +275,11 @@ struct Link<WD_F16> {
         }
         reconstruct_row2(u);
     }
+    // the link as packed halves (one complex per pair): rows 0 and 1 as
+    // stored, row 2 = conj(row0 x row1) formed with float accumulation and
+    // rounded to binary16
+    template <bool NT = false>
+    static __device__ __forceinline__ void load_h2(const void *g, int mu, int s, h2_t u[9]);
     static __device__ __forceinline__ void store(void *g, int mu, int s, const cx<double> u[9]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -274,6 +292,380 @@ struct Link<WD_F16> {
             q[3] = (_Float16)(float)u[2 * j + 1].im;
             *(h4_t *)elem(g, mu, s, j) = q;
         }
+    }
+};
+
+// ------------------------------------------------------------------ binary16 hops
+//
+// The binary16 stencil's link products on packed halves: a complex number is
+// one pair (re, im) of halves, and each real or imaginary part of a product
+// sum is a chain of two-term dot products of halves accumulated in float32
+// (v_dot2_f32_f16: the products of halves are exact in float32).  The
+// spin projection adds pairs of halves (the stored spinor is v / s with
+// |v / s| <= 1, so the sums stay within binary16's range); the site scale s
+// multiplies the hop's float result.
+
+// Two-term dot products of halves accumulated in float32, with the sign
+// modifiers of v_dot2_f32_f16 on the second operand's halves (the compiler
+// does not fold a negated half into the instruction and would spend a
+// separate instruction on it):
+//   dot2_pp(a, b, c) = a.x b.x + a.y b.y + c     dot2_pm = a.x b.x - a.y b.y + c
+//   dot2_mp          = -a.x b.x + a.y b.y + c    dot2_mm = -a.x b.x - a.y b.y + c
+// The *0 forms start a chain at c = 0.
+#define WD_DOT2(NAME, MODS)                                                                 \
+    __device__ __forceinline__ float NAME(h2_t a, h2_t b, float c) {                        \
+        float d;                                                                            \
+        asm("v_dot2_f32_f16 %0, %1, %2, %3" MODS : "=v"(d) : "v"(a), "v"(b), "v"(c));       \
+        return d;                                                                           \
+    }                                                                                       \
+    __device__ __forceinline__ float NAME##0(h2_t a, h2_t b) {                              \
+        float d;                                                                            \
+        asm("v_dot2_f32_f16 %0, %1, %2, 0" MODS : "=v"(d) : "v"(a), "v"(b));                \
+        return d;                                                                           \
+    }
+WD_DOT2(dot2_pp, "")
+WD_DOT2(dot2_pm, " neg_hi:[0,1,0]")
+WD_DOT2(dot2_mp, " neg_lo:[0,1,0]")
+WD_DOT2(dot2_mm, " neg_lo:[0,1,0] neg_hi:[0,1,0]")
+#undef WD_DOT2
+
+__device__ __forceinline__ h2_t h2_swap(h2_t b) { return __builtin_shufflevector(b, b, 1, 0); }
+
+// the sign modifiers of the dot products (WD_H2_MODS 1), or explicit
+// negated / swapped operand pairs and the plain instruction (0)
+#ifndef WD_H2_MODS
+#define WD_H2_MODS 0
+#endif
+
+__device__ __forceinline__ float dot2(h2_t a, h2_t b, float c) {
+    return __builtin_amdgcn_fdot2(a, b, c, false);
+}
+
+template <bool NT>
+__device__ __forceinline__ void Link<WD_F16>::load_h2(const void *g, int mu, int s, h2_t u[9]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const h4_t q = ldv<NT>((const h4_t *)elem(g, mu, s, j));
+        u[2 * j] = h2_t{q[0], q[1]};
+        u[2 * j + 1] = h2_t{q[2], q[3]};
+    }
+    // row 2 = conj(u0[j1] u1[j2] - u0[j2] u1[j1]): re(ab - cd) = a.b(-) - c.d(-),
+    // im(ab - cd) = a.swap(b) - c.swap(d)
+#if WD_H2_MODS
+    h2_t s1[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s1[j] = h2_swap(u[3 + j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const float re = dot2_pm(u[j1], u[3 + j2], dot2_mp0(u[j2], u[3 + j1]));
+        const float im = dot2_pp(u[j1], s1[j2], dot2_mm0(u[j2], s1[j1]));
+        u[6 + j] = h2_t{(_Float16)re, (_Float16)(-im)};
+    }
+#else
+    // operand pairs of the row-1 entries: (x, -y), (y, x), (-x, y), (-y, -x)
+    h2_t bc[3], bs[3], dn[3], dsn[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const h2_t b = u[3 + j];
+        bc[j] = h2_t{b.x, -b.y};
+        bs[j] = h2_t{b.y, b.x};
+        dn[j] = h2_t{-b.x, b.y};
+        dsn[j] = h2_t{-b.y, -b.x};
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const float re = dot2(u[j1], bc[j2], dot2(u[j2], dn[j1], 0.f));
+        const float im = dot2(u[j1], bs[j2], dot2(u[j2], dsn[j1], 0.f));
+        u[6 + j] = h2_t{(_Float16)re, (_Float16)(-im)};
+    }
+#endif
+}
+
+// (1 + S gamma_mu) psi on packed halves: the two upper spin components
+template <int MU, int S>
+__device__ __forceinline__ void project_h2(const h2_t p[12], h2_t h0[3], h2_t h1[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h2_t a0 = p[c], a1 = p[3 + c], a2 = p[6 + c], a3 = p[9 + c];
+        if (MU == 0) {
+            const h2_t i3{-a3.y, a3.x}, i2{-a2.y, a2.x};
+            h0[c] = S > 0 ? a0 + i3 : a0 - i3;
+            h1[c] = S > 0 ? a1 + i2 : a1 - i2;
+        } else if (MU == 1) {
+            h0[c] = S > 0 ? a0 - a3 : a0 + a3;
+            h1[c] = S > 0 ? a1 + a2 : a1 - a2;
+        } else if (MU == 2) {
+            const h2_t i2{-a2.y, a2.x}, i3{-a3.y, a3.x};
+            h0[c] = S > 0 ? a0 + i2 : a0 - i2;
+            h1[c] = S > 0 ? a1 - i3 : a1 + i3;
+        } else {
+            h0[c] = S > 0 ? a0 + a2 : a0 - a2;
+            h1[c] = S > 0 ? a1 + a3 : a1 - a3;
+        }
+    }
+}
+
+// w = U h (ADJ: U^dag h) in float32 from packed halves:
+//   U h:     re = U.x h.x - U.y h.y,  im = U.x h.y + U.y h.x = U . swap(h)
+//   U^dag h: re = U.x h.x + U.y h.y,  im = U.x h.y - U.y h.x = U . swap(h)(-)
+template <bool ADJ>
+__device__ __forceinline__ void su3_mul_h2(const h2_t u[9], const h2_t h[3], cx<float> w[3]) {
+#if WD_H2_MODS
+    h2_t hs[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) hs[b] = h2_swap(h[b]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const h2_t m0 = ADJ ? u[a] : u[3 * a], m1 = ADJ ? u[3 + a] : u[3 * a + 1],
+                   m2 = ADJ ? u[6 + a] : u[3 * a + 2];
+        float re, im;
+        if (ADJ) {
+            re = dot2_pp(m2, h[2], dot2_pp(m1, h[1], dot2_pp0(m0, h[0])));
+            im = dot2_pm(m2, hs[2], dot2_pm(m1, hs[1], dot2_pm0(m0, hs[0])));
+        } else {
+            re = dot2_pm(m2, h[2], dot2_pm(m1, h[1], dot2_pm0(m0, h[0])));
+            im = dot2_pp(m2, hs[2], dot2_pp(m1, hs[1], dot2_pp0(m0, hs[0])));
+        }
+        w[a] = {re, im};
+    }
+#else
+    // operand pairs: U h takes (h.x, -h.y) and (h.y, h.x); U^dag h takes h
+    // itself and (h.y, -h.x)
+    h2_t hr[3], hi[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        hr[b] = ADJ ? h[b] : h2_t{h[b].x, -h[b].y};
+        hi[b] = ADJ ? h2_t{h[b].y, -h[b].x} : h2_t{h[b].y, h[b].x};
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const h2_t m0 = ADJ ? u[a] : u[3 * a], m1 = ADJ ? u[3 + a] : u[3 * a + 1],
+                   m2 = ADJ ? u[6 + a] : u[3 * a + 2];
+        const float re = dot2(m2, hr[2], dot2(m1, hr[1], dot2(m0, hr[0], 0.f)));
+        const float im = dot2(m2, hi[2], dot2(m1, hi[1], dot2(m0, hi[0], 0.f)));
+        w[a] = {re, im};
+    }
+#endif
+}
+
+// acc += s * (the hop result rebuilt to four spins), as accumulate(), with
+// the site scale folded into fused multiply-adds
+template <int MU, int S>
+__device__ __forceinline__ void accumulate_s(float s, const cx<float> w0[3],
+                                             const cx<float> w1[3], cx<float> acc[12]) {
+    auto add = [](cx<float> &a, float f, cx<float> w) {  // a += f w
+        a = {fmaf(f, w.re, a.re), fmaf(f, w.im, a.im)};
+    };
+    auto add_i = [](cx<float> &a, float f, cx<float> w) {  // a += f i w
+        a = {fmaf(-f, w.im, a.re), fmaf(f, w.re, a.im)};
+    };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        add(acc[c], s, w0[c]);
+        add(acc[3 + c], s, w1[c]);
+        if (MU == 0) {  // lower: -S i w1, -S i w0
+            add_i(acc[6 + c], S > 0 ? -s : s, w1[c]);
+            add_i(acc[9 + c], S > 0 ? -s : s, w0[c]);
+        } else if (MU == 1) {  // lower: S w1, -S w0
+            add(acc[6 + c], S > 0 ? s : -s, w1[c]);
+            add(acc[9 + c], S > 0 ? -s : s, w0[c]);
+        } else if (MU == 2) {  // lower: -S i w0, S i w1
+            add_i(acc[6 + c], S > 0 ? -s : s, w0[c]);
+            add_i(acc[9 + c], S > 0 ? s : -s, w1[c]);
+        } else {  // lower: S w0, S w1
+            add(acc[6 + c], S > 0 ? s : -s, w0[c]);
+            add(acc[9 + c], S > 0 ? s : -s, w1[c]);
+        }
+    }
+}
+
+// 8 reals per link in binary16 (16 bytes): a parametrisation of SU(3) in
+// which no stored quantity is recovered from a difference of nearly equal
+// numbers, so binary16 rounding is not amplified.  Columns are first
+// relabelled cyclically by j (a cyclic relabelling keeps the matrix special
+// unitary), so that entry a_j of row 0 with the largest modulus comes first:
+// row 0 = (a_j, a_p, a_q), p = j+1, q = j+2 (mod 3).
+//  - Row 0: a_p and a_q are stored (4 reals) and one component of a_j, the
+//    other being +-sqrt(1 - |a_p|^2 - |a_q|^2 - comp^2), the larger of the two
+//    (|a_j|^2 >= 1/3, so the root is taken of at least 1/6).
+//  - A frame of the plane orthogonal to row 0: e1 = conj(row0 x e_k) / norm,
+//    with e_k the unit vector at k = p or q, the smaller of the two entries
+//    (the norm^2 = 1 - |a_k|^2 >= 2/3), and e2 = conj(row0 x e1); the rows
+//    (row0, e1, e2) are special unitary.
+//  - Row 1 = alpha e1 + beta e2 with |alpha|^2 + |beta|^2 = 1; the smaller of
+//    alpha, beta is stored (2 reals) and one component of the larger, the
+//    other derived as above.  Row 2 = conj(row0 x row1) = conj(alpha) e2 -
+//    conj(beta) e1.
+// The eight choices (j: 2 bits; which component of a_j and its sign; k; which
+// of alpha, beta is stored; which component of the other and its sign) sit
+// in the lowest significand bit of the eight halves: each value is rounded
+// to the nearest binary16 number whose last bit is the choice bit (at most
+// one unit in the last place off).
+// Slots: 0,1 a_p; 2,3 a_q; 4 the stored component of a_j; 5,6 the stored one
+// of alpha/beta; 7 the stored component of the other.  Bits (slot: meaning):
+// 0,1 j; 2 a_j's derived component is Im; 3 it is negative; 4 k = q; 5 alpha
+// is the stored one; 6 the other's derived component is Im; 7 it is negative.
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+
+// the binary16 number nearest to x whose last significand bit is `bit`
+__device__ __forceinline__ unsigned short half_with_bit(double x, int bit) {
+    const _Float16 h = (_Float16)(float)x;
+    const unsigned short b = __builtin_bit_cast(unsigned short, h);
+    if ((b & 1) == bit) return b;
+    const unsigned short sgn = b & 0x8000, mag = b & 0x7fff;
+    if (mag == 0) return (unsigned short)(sgn | 1);
+    const unsigned short dn = (unsigned short)(sgn | (mag - 1));
+    const unsigned short up = (unsigned short)(sgn | (mag + 1));
+    const double vd = (double)__builtin_bit_cast(_Float16, dn);
+    const double vu = (double)__builtin_bit_cast(_Float16, up);
+    return fabs(vd - x) <= fabs(vu - x) ? dn : up;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> cross_entry(const cx<R> a[3], const cx<R> b[3], int i) {
+    // (a x b)_i = a_{i+1} b_{i+2} - a_{i+2} b_{i+1}
+    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+    return cmul(a[i1], b[i2]) - cmul(a[i2], b[i1]);
+}
+
+// Rows 1 and 2 from row 0 (columns already relabelled), the pivot choice and
+// the stored alpha/beta part; shared by the encoder's check and the decoder.
+template <typename R>
+__device__ __forceinline__ void r8_frame(const cx<R> r0[3], int kq, cx<R> e1[3], cx<R> e2[3]) {
+    // c = row0 x e_k in the relabelled columns: k = p gives (-a_q, 0, a_j),
+    // k = q gives (a_p, -a_j, 0)
+    cx<R> c[3];
+    R ak2;
+    if (kq) {
+        c[0] = r0[1];
+        c[1] = -r0[0];
+        c[2] = {R(0), R(0)};
+        ak2 = norm2(r0[2]);
+    } else {
+        c[0] = -r0[2];
+        c[1] = {R(0), R(0)};
+        c[2] = r0[0];
+        ak2 = norm2(r0[1]);
+    }
+    const R inv = R(1) / sqrt(R(1) - ak2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) e1[i] = scale(inv, conj(c[i]));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) e2[i] = conj(cross_entry(r0, e1, i));
+}
+
+// the derived component: +-sqrt(1 - sum of squares of the stored ones)
+template <typename R>
+__device__ __forceinline__ cx<R> r8_derive(R s0, R s1, R s2, R s3, R comp, int im, int neg) {
+    const R m = R(1) - (s0 * s0 + s1 * s1 + s2 * s2 + s3 * s3 + comp * comp);
+    R d = sqrt(m > R(0) ? m : R(0));
+    if (neg) d = -d;
+    return im ? cx<R>{comp, d} : cx<R>{d, comp};
+}
+
+template <typename R>
+__device__ __forceinline__ void r8_decode(const R f[8], const int b[8], cx<R> u[9]) {
+    const int j = b[0] | (b[1] << 1);
+    cx<R> r0[3];
+    r0[1] = {f[0], f[1]};
+    r0[2] = {f[2], f[3]};
+    r0[0] = r8_derive(f[0], f[1], f[2], f[3], f[4], b[2], b[3]);
+    cx<R> e1[3], e2[3];
+    r8_frame(r0, b[4], e1, e2);
+    const cx<R> g{f[5], f[6]};
+    const cx<R> d = r8_derive(f[5], f[6], R(0), R(0), f[7], b[6], b[7]);
+    const cx<R> al = b[5] ? g : d, be = b[5] ? d : g;
+    cx<R> w[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        w[i] = r0[i];
+        w[3 + i] = cmul(al, e1[i]) + cmul(be, e2[i]);
+        w[6 + i] = cmul(conj(al), e2[i]) - cmul(conj(be), e1[i]);
+    }
+    // undo the column relabelling: column (j + c) mod 3 of U is column c
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const cx<R> x0 = w[3 * r], x1 = w[3 * r + 1], x2 = w[3 * r + 2];
+        u[3 * r + 0] = j == 0 ? x0 : (j == 1 ? x2 : x1);
+        u[3 * r + 1] = j == 0 ? x1 : (j == 1 ? x0 : x2);
+        u[3 * r + 2] = j == 0 ? x2 : (j == 1 ? x1 : x0);
+    }
+}
+
+template <>
+struct Link<kLinkF16R8> {
+    using R = float;
+    static constexpr size_t kTileBytes = 4 * 1024;
+    static __device__ __forceinline__ const char *elem(const void *g, int mu, int s) {
+        return (const char *)g + (size_t)(s >> 6) * kTileBytes + mu * 1024 + (s & 63) * 16;
+    }
+    template <bool NT = false>
+    static __device__ __forceinline__ void load(const void *g, int mu, int s, cx<R> u[9]) {
+        const h8_t q = ldv<NT>((const h8_t *)elem(g, mu, s));
+        const u16x8_t raw = __builtin_bit_cast(u16x8_t, q);
+        R f[8];
+        int b[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            f[i] = (R)q[i];
+            b[i] = raw[i] & 1;
+        }
+        r8_decode(f, b, u);
+    }
+    static __device__ __forceinline__ void store(void *g, int mu, int s, const cx<double> u[9]) {
+        // relabel columns so that the largest entry of row 0 comes first
+        const double m0 = norm2(u[0]), m1 = norm2(u[1]), m2 = norm2(u[2]);
+        const int j = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
+        cx<double> r0[3], r1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r0[c] = u[(j + c) % 3];
+            r1[c] = u[3 + (j + c) % 3];
+        }
+        unsigned short h[8];
+        int b[8];
+        b[0] = j & 1;
+        b[1] = j >> 1;
+        b[2] = fabs(r0[0].im) > fabs(r0[0].re) ? 1 : 0;  // derive the larger component
+        const double dv = b[2] ? r0[0].im : r0[0].re;
+        b[3] = dv < 0 ? 1 : 0;
+        h[0] = half_with_bit(r0[1].re, b[0]);
+        h[1] = half_with_bit(r0[1].im, b[1]);
+        h[2] = half_with_bit(r0[2].re, b[2]);
+        h[3] = half_with_bit(r0[2].im, b[3]);
+        double f[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = (double)__builtin_bit_cast(_Float16, h[i]);
+        // the pivot of the frame: the smaller of the stored a_p, a_q as they
+        // decode
+        b[4] = f[2] * f[2] + f[3] * f[3] < f[0] * f[0] + f[1] * f[1] ? 1 : 0;
+        h[4] = half_with_bit(b[2] ? r0[0].re : r0[0].im, b[4]);
+        f[4] = (double)__builtin_bit_cast(_Float16, h[4]);
+        // the frame as the decoder rebuilds it from the rounded row 0
+        cx<double> d0[3], e1[3], e2[3];
+        d0[1] = {f[0], f[1]};
+        d0[2] = {f[2], f[3]};
+        d0[0] = r8_derive(f[0], f[1], f[2], f[3], f[4], b[2], b[3]);
+        r8_frame(d0, b[4], e1, e2);
+        cx<double> al{0.0, 0.0}, be{0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            al = cfmac(e1[i], r1[i], al);  // <e1, r1>
+            be = cfmac(e2[i], r1[i], be);  // <e2, r1>
+        }
+        b[5] = norm2(al) < norm2(be) ? 1 : 0;  // store the smaller
+        const cx<double> gs = b[5] ? al : be, dl = b[5] ? be : al;
+        b[6] = fabs(dl.im) > fabs(dl.re) ? 1 : 0;
+        b[7] = (b[6] ? dl.im : dl.re) < 0 ? 1 : 0;
+        h[5] = half_with_bit(gs.re, b[5]);
+        h[6] = half_with_bit(gs.im, b[6]);
+        h[7] = half_with_bit(b[6] ? dl.re : dl.im, b[7]);
+        u16x8_t raw;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) raw[i] = h[i];
+        *(h8_t *)elem(g, mu, s) = __builtin_bit_cast(h8_t, raw);
     }
 };
 

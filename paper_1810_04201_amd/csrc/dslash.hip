@@ -49,6 +49,11 @@
 #ifndef WD_NT_OUT
 #define WD_NT_OUT 1
 #endif
+// binary16 hops (12-real links) with their link products on packed halves
+// (v_dot2_f32_f16) instead of float32 operands
+#ifndef WD_F16_DOT2
+#define WD_F16_DOT2 0
+#endif
 // the marching stencil's fused r update: load r at the start of the step
 // (its latency hidden behind the hops) instead of after them; per
 // precision bit: 1 float64, 2 float32, 4 binary16
@@ -59,6 +64,7 @@
 #ifndef WD_NT_RLOAD
 #define WD_NT_RLOAD 1
 #endif
+
 
 namespace wd {
 
@@ -133,6 +139,21 @@ __device__ __forceinline__ void hop(const void *gauge, const FieldRef &in, int n
                                     int link_site, bool negate,
                                     cx<typename Spinor<PREC>::R> acc[12]) {
     using R = typename Spinor<PREC>::R;
+    if constexpr (PREC == WD_F16 && LF == WD_F16 && WD_F16_DOT2) {
+        h2_t q[12];
+        float sc;
+        Spinor<WD_F16>::load_raw(in, nbr_entry, q, sc);
+        h2_t h0[3], h1[3];
+        project_h2<MU, S>(q, h0, h1);
+        h2_t u[9];
+        Link<WD_F16>::load_h2<false>(gauge, MU, link_site, u);
+        cx<float> w0[3], w1[3];
+        su3_mul_h2<BWD>(u, h0, w0);
+        su3_mul_h2<BWD>(u, h1, w1);
+        // the antiperiodic boundary sign rides on the site scale
+        accumulate_s<MU, S>(MU == 3 && negate ? -sc : sc, w0, w1, acc);
+        return;
+    }
     cx<R> p[12];
     Spinor<PREC>::load(in, nbr_entry, p);
     cx<R> h0[3], h1[3];
@@ -234,8 +255,28 @@ __device__ __forceinline__ void hop_s(const void *gauge, const FieldRef &in, con
                                       int sbase, int wvol, int nbr, int link_site,
                                       cx<typename Spinor<PREC>::R> acc[12]) {
     using R = typename Spinor<PREC>::R;
-    cx<R> p[12];
     const int d = nbr - sbase;
+    if constexpr (PREC == WD_F16 && LF == WD_F16 && WD_F16_DOT2) {
+        h2_t q[12];
+        float sc;
+        if ((unsigned)d < (unsigned)wvol)
+            Spinor<WD_F16>::load_raw(cur, d, q, sc);
+        else
+            Spinor<WD_F16>::load_raw(in, nbr, q, sc);
+        h2_t h0[3], h1[3];
+        project_h2<MU, S>(q, h0, h1);
+        h2_t u[9];
+        Link<WD_F16>::load_h2<WD_NT_LINK && !BWD>(gauge, MU, link_site, u);
+        cx<float> w0[3], w1[3];
+        su3_mul_h2<BWD>(u, h0, w0);
+        su3_mul_h2<BWD>(u, h1, w1);
+        accumulate_s<MU, S>(sc, w0, w1, acc);
+        return;
+    }
+    cx<R> p[12];
+    // the compiler merges the two loads into one flat load on the selected
+    // pointer (LDS or memory); separate LDS-typed and global loads measured
+    // four times slower in float64 (both paths' registers live at once)
     if ((unsigned)d < (unsigned)wvol)
         Spinor<PREC>::load(cur, d, p);
     else
@@ -250,7 +291,7 @@ __device__ __forceinline__ void hop_s(const void *gauge, const FieldRef &in, con
     accumulate<MU, S>(w0, w1, acc);
 }
 
-template <int PREC, bool DAG, bool RED, int GROUP>
+template <int PREC, bool DAG, bool RED, int GROUP, int LF = PREC>
 __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__ gauge, FieldRef in,
                                                 FieldRef out, double kappa_d, RedArgs red,
                                                 Gate gate) {
@@ -285,21 +326,21 @@ __global__ void __launch_bounds__(256) k_dslash(Geom g, const void *__restrict__
         // memory-level parallelism).
 #define WD_HOP_FENCE(k) \
     if ((k) % GROUP == 0) __builtin_amdgcn_sched_barrier(0)
-        hop<0, SF, false, PREC>(gauge, fin, xp, site, false, acc);
+        hop<0, SF, false, PREC, LF>(gauge, fin, xp, site, false, acc);
         WD_HOP_FENCE(1);
-        hop<0, SB, true, PREC>(gauge, fin, xm, xm, false, acc);
+        hop<0, SB, true, PREC, LF>(gauge, fin, xm, xm, false, acc);
         WD_HOP_FENCE(2);
-        hop<1, SF, false, PREC>(gauge, fin, yp, site, false, acc);
+        hop<1, SF, false, PREC, LF>(gauge, fin, yp, site, false, acc);
         WD_HOP_FENCE(3);
-        hop<1, SB, true, PREC>(gauge, fin, ym, ym, false, acc);
+        hop<1, SB, true, PREC, LF>(gauge, fin, ym, ym, false, acc);
         WD_HOP_FENCE(4);
-        hop<2, SF, false, PREC>(gauge, fin, zp, site, false, acc);
+        hop<2, SF, false, PREC, LF>(gauge, fin, zp, site, false, acc);
         WD_HOP_FENCE(5);
-        hop<2, SB, true, PREC>(gauge, fin, zm, zm, false, acc);
+        hop<2, SB, true, PREC, LF>(gauge, fin, zm, zm, false, acc);
         WD_HOP_FENCE(6);
-        hop<3, SF, false, PREC>(gauge, fin, tp, site, neg_tp, acc);
+        hop<3, SF, false, PREC, LF>(gauge, fin, tp, site, neg_tp, acc);
         WD_HOP_FENCE(7);
-        hop<3, SB, true, PREC>(gauge, fin, tm, tm, neg_tm, acc);
+        hop<3, SB, true, PREC, LF>(gauge, fin, tm, tm, neg_tm, acc);
         WD_HOP_FENCE(8);
 #undef WD_HOP_FENCE
 
@@ -325,7 +366,7 @@ __device__ __forceinline__ double xr_site_r(const XrArgs &a, int rhs, int i,
                                             typename Spinor<PREC>::R alpha,
                                             const cx<typename Spinor<PREC>::R> q[12],
                                             cx<typename Spinor<PREC>::R> v[12]) {
-    constexpr int PX = PREC == WD_F64 ? WD_F64 : WD_F32;
+    constexpr int PX = xr_prec_of(PREC);
     double nrm = 0.0;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -340,7 +381,7 @@ template <int PREC>
 __device__ __forceinline__ double xr_site(const XrArgs &a, int rhs, int i,
                                           typename Spinor<PREC>::R alpha,
                                           const cx<typename Spinor<PREC>::R> q[12]) {
-    constexpr int PX = PREC == WD_F64 ? WD_F64 : WD_F32;
+    constexpr int PX = xr_prec_of(PREC);
     using R = typename Spinor<PREC>::R;
     cx<R> v[12];
     Spinor<PX>::load(rhs_view(a.r, rhs), i, v);
@@ -473,7 +514,7 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
         constexpr bool XPRE = XR && ((WD_XR_PREFETCH >> PREC) & 1);
         cx<R> rpre[XPRE ? 12 : 1];
         if constexpr (XPRE)
-            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::template load<WD_NT_RLOAD>(
+            Spinor<xr_prec_of(PREC)>::template load<WD_NT_RLOAD>(
                 rhs_view(xr.r, rhs), i, rpre);
         const Nbrs nb = neighbours(g, i);
         cx<R> acc[12];
@@ -494,22 +535,56 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_dslash_tm(Geom g, const void *_
         hop_s<2, SB, true, PREC, LF>(gauge, fin, cur, sbase, wvol, nb.zm, nb.zm, acc);
         WD_HOP_FENCE(6);
 #undef WD_HOP_FENCE
-        cx<R> ut[9];
-        Link<LF>::template load<WD_NT_LINK || WD_NT_LINK_T>(gauge, 3, i, ut);
+        // binary16 with 12-real links: the t hops on packed halves too
+        constexpr bool H2 = PREC == WD_F16 && LF == WD_F16 && WD_F16_DOT2;
+        cx<R> ut[H2 ? 1 : 9];
+        h2_t ut2[H2 ? 9 : 1];
+        if constexpr (H2)
+            Link<WD_F16>::template load_h2<WD_NT_LINK || WD_NT_LINK_T>(gauge, 3, i, ut2);
+        else
+            Link<LF>::template load<WD_NT_LINK || WD_NT_LINK_T>(gauge, 3, i, ut);
         // the next slice has landed in LDS (every wave's copy)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        {
-            cx<R> nx[12];
-            Spinor<PREC>::load(nxt, l, nx);
-            hop_p<3, SF, false>(nx, ut, g.antiperiodic && t == Lt - 1 && (!HALO || halo.last),
-                                acc);
-        }
-        accumulate<3, SB>(cw0, cw1, acc);
+        const bool neg_tp = g.antiperiodic && t == Lt - 1 && (!HALO || halo.last);
         cx<R> c[12];
-        Spinor<PREC>::load(cur, l, c);
-        // carry for slice t + 1 (never crosses the boundary inside a chunk)
-        {
+        if constexpr (H2) {
+            {
+                h2_t q[12];
+                float sc;
+                Spinor<WD_F16>::load_raw(nxt, l, q, sc);
+                h2_t h0[3], h1[3];
+                project_h2<3, SF>(q, h0, h1);
+                cx<float> w0[3], w1[3];
+                su3_mul_h2<false>(ut2, h0, w0);
+                su3_mul_h2<false>(ut2, h1, w1);
+                accumulate_s<3, SF>(neg_tp ? -sc : sc, w0, w1, acc);
+            }
+            accumulate<3, SB>(cw0, cw1, acc);
+            h2_t q[12];
+            float sc;
+            Spinor<WD_F16>::load_raw(cur, l, q, sc);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) c[k] = {sc * (float)q[k].x, sc * (float)q[k].y};
+            // carry for slice t + 1, scaled here as the float carry is
+            h2_t h0[3], h1[3];
+            project_h2<3, SB>(q, h0, h1);
+            su3_mul_h2<true>(ut2, h0, cw0);
+            su3_mul_h2<true>(ut2, h1, cw1);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cw0[k] = scale(sc, cw0[k]);
+                cw1[k] = scale(sc, cw1[k]);
+            }
+        } else {
+            {
+                cx<R> nx[12];
+                Spinor<PREC>::load(nxt, l, nx);
+                hop_p<3, SF, false>(nx, ut, neg_tp, acc);
+            }
+            accumulate<3, SB>(cw0, cw1, acc);
+            Spinor<PREC>::load(cur, l, c);
+            // carry for slice t + 1 (never crosses the boundary inside a chunk)
             cx<R> h0[3], h1[3];
             project<3, SB>(c, h0, h1);
             su3_mul<true>(ut, h0, cw0);
@@ -623,7 +698,7 @@ static void launch_tm(const Geom &g, const void *gauge, double kappa, int dagger
     if (red) launch_finalize(r, g.V / wvol, gate.batch ? gate.mode : -1, s);
 }
 
-template <int PREC>
+template <int PREC, int LF = PREC>
 static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagger, FieldRef in,
                         FieldRef out, const RedArgs *red, Gate gate, hipStream_t s,
                         const void *g12) {
@@ -635,7 +710,7 @@ static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagg
         if (PREC == WD_F64 && g12)
             launch_tm<WD_F64, kLinkF64R12>(g, g12, kappa, dagger, in, out, red, gate, s);
         else
-            launch_tm<PREC>(g, gauge, kappa, dagger, in, out, red, gate, s);
+            launch_tm<PREC, LF>(g, gauge, kappa, dagger, in, out, red, gate, s);
         return;
     }
     const int nb = site_blocks(g.V);
@@ -645,14 +720,14 @@ static void launch_prec(const Geom &g, const void *gauge, double kappa, int dagg
     constexpr int G = HopGroup<PREC>::value;
     if (dagger) {
         if (red)
-            hipLaunchKernelGGL((k_dslash<PREC, true, true, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, true, true, G, LF>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
         else
-            hipLaunchKernelGGL((k_dslash<PREC, true, false, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, true, false, G, LF>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
     } else {
         if (red)
-            hipLaunchKernelGGL((k_dslash<PREC, false, true, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, false, true, G, LF>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
         else
-            hipLaunchKernelGGL((k_dslash<PREC, false, false, G>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
+            hipLaunchKernelGGL((k_dslash<PREC, false, false, G, LF>), grid, bs, 0, s, g, gauge, in, out, kappa, r, gate);
     }
     if (red) launch_finalize(r, nb, gate.batch ? gate.mode : -1, s);
 }
@@ -662,7 +737,13 @@ void launch_dslash(const Geom &g, const void *gauge, double kappa, int dagger, F
     switch (in.prec) {
         case WD_F64: launch_prec<WD_F64>(g, gauge, kappa, dagger, in, out, red, gate, s, g12); break;
         case WD_F32: launch_prec<WD_F32>(g, gauge, kappa, dagger, in, out, red, gate, s, nullptr); break;
-        default: launch_prec<WD_F16>(g, gauge, kappa, dagger, in, out, red, gate, s, nullptr); break;
+        default:
+            if (g.f16_links8)
+                launch_prec<WD_F16, kLinkF16R8>(g, gauge, kappa, dagger, in, out, red, gate, s,
+                                                nullptr);
+            else
+                launch_prec<WD_F16>(g, gauge, kappa, dagger, in, out, red, gate, s, nullptr);
+            break;
     }
 }
 
@@ -716,7 +797,10 @@ bool launch_dslash_xr(const Geom &g, const void *gauge, double kappa, int dagger
                 return xr_prec<WD_F64, kLinkF64R12>(g, g12, kappa, dagger, in, xr, red, gate, s);
             return xr_prec<WD_F64>(g, gauge, kappa, dagger, in, xr, red, gate, s);
         case WD_F32: return xr_prec<WD_F32>(g, gauge, kappa, dagger, in, xr, red, gate, s);
-        default: return xr_prec<WD_F16>(g, gauge, kappa, dagger, in, xr, red, gate, s);
+        default:
+            if (g.f16_links8)
+                return xr_prec<WD_F16, kLinkF16R8>(g, gauge, kappa, dagger, in, xr, red, gate, s);
+            return xr_prec<WD_F16>(g, gauge, kappa, dagger, in, xr, red, gate, s);
     }
 }
 
@@ -885,7 +969,7 @@ __global__ void __launch_bounds__(kTmMaxBlock) k_hop_half_tm(Geom g, const void 
         constexpr bool XPRE = XR && ((WD_XR_PREFETCH >> PREC) & 1) && LF != WD_F64;
         cx<R> rpre[XPRE ? 12 : 1];
         if constexpr (XPRE)
-            Spinor<PREC == WD_F64 ? WD_F64 : WD_F32>::template load<WD_NT_RLOAD>(
+            Spinor<xr_prec_of(PREC)>::template load<WD_NT_RLOAD>(
                 rhs_view(xr.r, rhs), H, rpre);
         const Nbrs nb = neighbours(g, site_of_half(g, H, p));
         cx<R> acc[12];
@@ -1061,7 +1145,12 @@ void launch_hop_half_xr(const Geom &g, const void *gp, const void *gq, int p, do
             launch_hop_half_xr_prec<WD_F32>(g, gp, gq, p, k, cs, dagger, in, c, xr, red, gate, s);
             break;
         default:
-            launch_hop_half_xr_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, xr, red, gate, s);
+            if (g.f16_links8)
+                launch_hop_half_xr_prec<WD_F16, kLinkF16R8>(g, gp, gq, p, k, cs, dagger, in, c,
+                                                             xr, red, gate, s);
+            else
+                launch_hop_half_xr_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, xr, red, gate,
+                                                s);
             break;
     }
 }
@@ -1078,7 +1167,14 @@ void launch_hop_half(const Geom &g, const void *gp, const void *gq, int p, doubl
                 launch_hop_half_prec<WD_F64>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s);
             break;
         case WD_F32: launch_hop_half_prec<WD_F32>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
-        default: launch_hop_half_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate, s); break;
+        default:
+            if (g.f16_links8)
+                launch_hop_half_prec<WD_F16, kLinkF16R8>(g, gp, gq, p, k, cs, dagger, in, c, out,
+                                                         red, gate, s);
+            else
+                launch_hop_half_prec<WD_F16>(g, gp, gq, p, k, cs, dagger, in, c, out, red, gate,
+                                             s);
+            break;
     }
 }
 

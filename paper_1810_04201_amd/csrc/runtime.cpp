@@ -59,13 +59,15 @@ void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err) {
     }
     if (lat->gauge[prec]) return lat->gauge[prec];
     void *p = nullptr;
-    hipError_t he = hipMalloc(&p, gauge_bytes(prec, lat->g.V));
+    const int form = link_form(lat->g, prec);
+    hipError_t he = hipMalloc(&p, gauge_bytes(form, lat->g.V));
     if (he != hipSuccess) {
         *err = fail(WD_ERR_NOMEM, "hipMalloc of the %s gauge form failed: %s",
-                    prec == WD_F32 ? "F32-12" : "F16-12", hipGetErrorString(he));
+                    prec == WD_F32 ? "F32-12" : (form == kLinkF16R8 ? "F16-8" : "F16-12"),
+                    hipGetErrorString(he));
         return nullptr;
     }
-    launch_gauge_lo(lat->gauge[WD_F64], p, prec, lat->g.V, s);
+    launch_gauge_lo(lat->gauge[WD_F64], p, form, lat->g.V, s);
     // other streams (server slots) may use the form next: finish building it
     if (hipStreamSynchronize(s) != hipSuccess) {
         (void)hipFree(p);
@@ -89,7 +91,7 @@ bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[
     if (!lat->gauge_eo[prec][0]) {
         void *h[2] = {nullptr, nullptr};
         // float64 halves as 12 reals when the full-lattice links have that form
-        const int form = prec == WD_F64 && lat->gauge12 ? kLinkF64R12 : prec;
+        const int form = prec == WD_F64 && lat->gauge12 ? kLinkF64R12 : link_form(lat->g, prec);
         const size_t bytes = gauge_bytes(form, lat->g.V / 2);
         for (int p = 0; p < 2; ++p) {
             if (hipMalloc(&h[p], bytes) != hipSuccess) {
@@ -113,6 +115,55 @@ bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[
     out[0] = lat->gauge_eo[prec][0];
     out[1] = lat->gauge_eo[prec][1];
     return true;
+}
+
+static size_t eo_form_bytes(const wd_lattice *lat, int prec) {
+    const int form = prec == WD_F64 && lat->gauge12 ? kLinkF64R12 : link_form(lat->g, prec);
+    return 2 * gauge_bytes(form, lat->g.V / 2);
+}
+
+void lattice_forms(wd_lattice *lat, size_t *master, size_t derived[kNumDerived]) {
+    std::lock_guard<std::mutex> lk(lat->mu);
+    const int V = lat->g.V;
+    *master = (lat->gauge[WD_F64] ? gauge_bytes(WD_F64, V) : 0) +
+              (lat->gauge12 ? gauge_bytes(kLinkF64R12, V) : 0);
+    derived[kFormF32] = lat->gauge[WD_F32] ? gauge_bytes(WD_F32, V) : 0;
+    derived[kFormF16] = lat->gauge[WD_F16] ? gauge_bytes(link_form(lat->g, WD_F16), V) : 0;
+    derived[kFormEo64] =
+        lat->gauge_eo[WD_F64][0]
+            ? 2 * gauge_bytes(lat->eo64_r12 ? kLinkF64R12 : WD_F64, V / 2)
+            : 0;
+    derived[kFormEo32] = lat->gauge_eo[WD_F32][0] ? eo_form_bytes(lat, WD_F32) : 0;
+    derived[kFormEo16] = lat->gauge_eo[WD_F16][0] ? eo_form_bytes(lat, WD_F16) : 0;
+}
+
+void release_form(wd_lattice *lat, int form) {
+    std::lock_guard<std::mutex> lk(lat->mu);
+    auto drop = [](void *&p) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    };
+    switch (form) {
+        case kFormF32: drop(lat->gauge[WD_F32]); break;
+        case kFormF16: drop(lat->gauge[WD_F16]); break;
+        case kFormEo64: drop(lat->gauge_eo[WD_F64][0]); drop(lat->gauge_eo[WD_F64][1]); break;
+        case kFormEo32: drop(lat->gauge_eo[WD_F32][0]); drop(lat->gauge_eo[WD_F32][1]); break;
+        case kFormEo16: drop(lat->gauge_eo[WD_F16][0]); drop(lat->gauge_eo[WD_F16][1]); break;
+        default: break;
+    }
+}
+
+void solve_forms(const wd_lattice *lat, const wd_solve_params &p, size_t out[kNumDerived]) {
+    for (int f = 0; f < kNumDerived; ++f) out[f] = 0;
+    const int prec = p.prec_inner;
+    if (p.form & WD_SOLVE_EVEN_ODD) {
+        out[kFormEo64] = eo_form_bytes(lat, WD_F64);
+        if (prec == WD_F32) out[kFormEo32] = eo_form_bytes(lat, WD_F32);
+        if (prec == WD_F16) out[kFormEo16] = eo_form_bytes(lat, WD_F16);
+    } else {
+        if (prec == WD_F32) out[kFormF32] = gauge_bytes(WD_F32, lat->g.V);
+        if (prec == WD_F16) out[kFormF16] = gauge_bytes(link_form(lat->g, WD_F16), lat->g.V);
+    }
 }
 
 // ------------------------------------------------------------------ timing
@@ -251,13 +302,14 @@ int wd_create_lattice(const int32_t dims[4], uint32_t bc_flags, wd_lattice **out
     // a few V); byte offsets are 64-bit
     if (V > ((int64_t)1 << 28))
         return fail(WD_ERR_ARG, "volume %lld too large (at most 2^28 sites)", (long long)V);
-    if (bc_flags & ~(uint32_t)(WD_BC_ANTIPERIODIC_T | WD_SIGN_PLUS_KAPPA))
+    if (bc_flags & ~(uint32_t)(WD_BC_ANTIPERIODIC_T | WD_SIGN_PLUS_KAPPA | WD_F16_LINKS_8))
         return fail(WD_ERR_ARG, "unknown lattice flags 0x%x", bc_flags);
     wd_lattice *lat = new (std::nothrow) wd_lattice();
     if (!lat) return fail(WD_ERR_NOMEM, "host allocation failed");
     for (int m = 0; m < 4; ++m) lat->g.L[m] = dims[m];
     lat->g.V = (int)V;
     lat->g.antiperiodic = (bc_flags & WD_BC_ANTIPERIODIC_T) ? 1 : 0;
+    lat->g.f16_links8 = (bc_flags & WD_F16_LINKS_8) ? 1 : 0;
     lat->hop_sign = (bc_flags & WD_SIGN_PLUS_KAPPA) ? 1.0 : -1.0;
     choose_bricks(lat->g);
     *out = lat;
@@ -268,6 +320,7 @@ int wd_destroy_lattice(wd_lattice *lat) {
     if (!lat) return fail(WD_ERR_ARG, "null lattice");
     if (lat->users.load() != 0)
         return fail(WD_ERR_STATE, "lattice still has %d requests on a server", lat->users.load());
+    servers_forget(lat);
     for (int p = 0; p < 3; ++p) {
         if (lat->gauge[p]) (void)hipFree(lat->gauge[p]);
         for (int q = 0; q < 2; ++q)
@@ -296,9 +349,10 @@ int wd_lattice_gauge_bytes(const wd_lattice *lat, size_t *bytes) {
     if (!lat || !bytes) return fail(WD_ERR_ARG, "null argument");
     size_t b = lat->gauge12 ? gauge_bytes(kLinkF64R12, lat->g.V) : 0;
     for (int p = 0; p < 3; ++p) {
-        if (lat->gauge[p]) b += gauge_bytes(p, lat->g.V);
+        if (lat->gauge[p]) b += gauge_bytes(link_form(lat->g, p), lat->g.V);
         if (lat->gauge_eo[p][0])
-            b += 2 * gauge_bytes(p == WD_F64 && lat->eo64_r12 ? kLinkF64R12 : p, lat->g.V / 2);
+            b += 2 * gauge_bytes(p == WD_F64 && lat->eo64_r12 ? kLinkF64R12 : link_form(lat->g, p),
+                                 lat->g.V / 2);
     }
     if (lat->halo_links) b += gauge_bytes(WD_F64, lat->g.V / lat->g.L[3]);
     *bytes = b;
@@ -311,6 +365,9 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
     std::lock_guard<std::mutex> lk(lat->mu);
     if (lat->users.load() != 0)
         return fail(WD_ERR_STATE, "gauge cannot change while requests are in flight");
+    // every resident form is rebuilt below; until all of them hold the new
+    // links (an early error return leaves them mixed) the lattice has none
+    lat->has_gauge = false;
     if (!lat->gauge[WD_F64]) {
         void *p = nullptr;
         hipError_t he = hipMalloc(&p, gauge_bytes(WD_F64, lat->g.V));
@@ -354,7 +411,8 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
         lat->gauge12 = nullptr;
     }
     for (int p = 1; p < 3; ++p)
-        if (lat->gauge[p]) launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], p, lat->g.V, s);
+        if (lat->gauge[p])
+            launch_gauge_lo(lat->gauge[WD_F64], lat->gauge[p], link_form(lat->g, p), lat->g.V, s);
     // float64 halves whose form no longer matches are dropped (rebuilt on use)
     if (lat->gauge_eo[WD_F64][0] && lat->eo64_r12 != (lat->gauge12 != nullptr)) {
         for (int q = 0; q < 2; ++q) {
@@ -366,7 +424,9 @@ int wd_set_gauge(wd_lattice *lat, const double *U, void *stream) {
         for (int q = 0; q < 2; ++q)
             if (lat->gauge_eo[p][q])
                 launch_gauge_split(lat->gauge[WD_F64], lat->gauge_eo[p][q],
-                                   p == WD_F64 && lat->eo64_r12 ? kLinkF64R12 : p, q, lat->g, s);
+                                   p == WD_F64 && lat->eo64_r12 ? kLinkF64R12
+                                                                : link_form(lat->g, p),
+                                   q, lat->g, s);
     WD_LAUNCH_CHECK();
     WD_HIP_CHECK(hipStreamSynchronize(s));
     lat->has_gauge = true;

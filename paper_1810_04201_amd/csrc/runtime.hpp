@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "server_core.hpp"
 #include "wd_internal.hpp"
 
 struct wd_lattice {
@@ -20,7 +21,7 @@ struct wd_lattice {
     bool eo64_r12 = false;    // gauge_eo[WD_F64] holds the F64-12 form
     void *gauge_eo[3][2] = {};                     // even-odd halves [prec][parity]
     void *halo_links = nullptr;                    // U_t(x, -1) over face sites (t-slab)
-    bool has_gauge = false;
+    std::atomic<bool> has_gauge{false};  // read without the lock by validation
     double hop_sign = -1.0;  // D = 1 + hop_sign * kappa * (hops); kernels take 1 - kappa' H
     std::mutex mu;
     std::atomic<int> users{0};  // requests in flight on a server
@@ -65,6 +66,21 @@ void *gauge_for(wd_lattice *lat, int prec, hipStream_t s, int *err);
 // even-odd half forms of a precision (both parities), built on first use
 // from the F64-18 tiles; false and the error set on failure
 bool gauge_eo_for(wd_lattice *lat, int prec, hipStream_t s, int *err, void *out[2]);
+
+// Resident gauge forms, for a server's HBM ledger (under the lattice lock):
+// *master = the float64 links (18 reals, plus 12 where kept), derived[f] the
+// bytes of each derived form (DerivedForm) now resident, 0 where not built.
+void lattice_forms(wd_lattice *lat, size_t *master, size_t derived[kNumDerived]);
+// Release one derived form of the lattice (it is rebuilt, bit for bit, on
+// next use).  The caller makes sure no queued work reads it.
+void release_form(wd_lattice *lat, int form);
+// Bytes of the derived forms a solve with parameters p reads (0 where it
+// reads none of that form).
+void solve_forms(const wd_lattice *lat, const wd_solve_params &p, size_t out[kNumDerived]);
+
+// A lattice is being destroyed: every live server drops it from its ledger
+// (server.cpp).
+void servers_forget(wd_lattice *lat);
 
 // out_p = cs * c_p + D_{p,1-p} in_{1-p} on half fields: the off-diagonal block
 // of D (D^dag for dagger) from parity 1-p to p at hopping parameter kappa

@@ -11,13 +11,23 @@
 // overlap on the GPU.  Each request owns its workspace and reductions, so its
 // result is bitwise the same alone or in any mix.
 //
-// HBM accounting: a request is charged its solver workspace; a lattice's
-// packed gauge forms are charged once while any admitted request uses them.
+// Locking: client threads (wd_submit, wd_poll) meet the scheduler only in the
+// ticket book, whose lock is held for a queue push, a result copy or a map
+// lookup.  Admission, kernel enqueues, graph captures and gauge-form builds
+// run without it, so clients never wait behind device work.  The HBM ledger
+// has a lock of its own, shared with wd_destroy_lattice (a destroyed lattice
+// leaves every server's ledger before its forms are freed).
+//
+// HBM accounting (Ledger): running requests' workspaces, the float64 links
+// of lattices with running requests, and every derived gauge form (float32,
+// binary16, even-odd halves) resident on a lattice the server has used, for
+// as long as it stays allocated.  A request that does not fit makes the
+// server release derived forms of lattices without running requests; they
+// are rebuilt on next use.
 #include <algorithm>
 #include <chrono>
-#include <condition_variable>
-#include <map>
 #include <memory>
+#include <set>
 #include <thread>
 
 #include "runtime.hpp"
@@ -25,19 +35,26 @@
 namespace wd {
 
 struct Request {
-    uint64_t ticket = 0;
+    // set by wd_submit before the ticket is issued, read-only afterwards
     wd_lattice *lat = nullptr;
     wd_solve_params p{};
     const double *b = nullptr;
     double *x = nullptr;
-    double t_submit = 0, t_admit = 0, t_done = 0;
-    int state = 0;  // 0 queued, 1 running, 2 done
+    double t_submit = 0;
+    // ticket book (under its lock)
+    uint64_t ticket = 0;
+    bool done = false;
     int rc = WD_PENDING;
     std::vector<wd_solve_info> info;
+    // scheduler thread only
     std::unique_ptr<Solve> solve;
-    size_t charged = 0;
+    Need need{};
+    double t_admit = 0;
     int slot = -1;
 };
+
+// finished tickets that stay pollable
+constexpr size_t kKeepFinished = 4096;
 
 }  // namespace wd
 
@@ -45,138 +62,128 @@ struct wd_server {
     wd_server_config cfg{};
     int device = 0;
     std::thread thr;
-    std::mutex mu;
-    std::condition_variable cv;
-    bool stopping = false;
-    uint64_t next_ticket = 1;
-    std::deque<uint64_t> queue;
-    std::map<uint64_t, std::shared_ptr<wd::Request>> reqs;
+    wd::TicketBook<wd::Request> book{wd::kKeepFinished};
+    // scheduler thread only
+    std::deque<std::shared_ptr<wd::Request>> queue;
     std::vector<std::shared_ptr<wd::Request>> active;
     std::vector<hipStream_t> streams;
+    bool own_streams = true;
     std::vector<wd::SlotRes> slots;
     std::vector<int> slot_busy;
-    // per lattice: admitted requests using it and the gauge forms charged
-    struct LatUse {
-        int users = 0;
-        size_t charged = 0;
-        bool form[3] = {false, false, false};  // full-lattice forms charged
-        bool eo[3] = {false, false, false};    // even-odd half forms charged
-    };
-    std::map<wd_lattice *, LatUse> lat_use;
-    size_t used = 0, peak = 0;
+    // HBM ledger (ledger_mu)
+    std::mutex ledger_mu;
+    wd::Ledger ledger{0};
+    // statistics (stat_mu)
+    std::mutex stat_mu;
     double t_start = 0, t_last = 0;
     std::vector<double> latencies;
 };
 
 namespace wd {
 
-static size_t request_bytes(const wd_lattice *lat, const wd_solve_params &p) {
-    return Solve::footprint(lat, p);
+// every live server, so that a destroyed lattice can leave their ledgers
+static std::mutex g_servers_mu;
+static std::set<wd_server *> g_servers;
+
+static Need request_need(const wd_lattice *lat, const wd_solve_params &p) {
+    Need n{};
+    n.workspace = Solve::footprint(lat, p);
+    solve_forms(lat, p, n.form_bytes);
+    return n;
 }
 
-static bool eo_request(const wd_solve_params &p) { return (p.form & WD_SOLVE_EVEN_ODD) != 0; }
-
-// gauge bytes a request needs on its lattice: the float64 tiles (always
-// there once the gauge is set), plus the forms its solve reads
-static size_t gauge_need(const wd_lattice *lat, const wd_solve_params &p, const bool form[3],
-                         const bool eo[3]) {
-    const int V = lat->g.V, prec = p.prec_inner;
-    // the float64 forms (F64-18, and F64-12 for special unitary links)
-    size_t b = form[WD_F64] ? 0
-                            : gauge_bytes(WD_F64, V) +
-                                  (lat->gauge12 ? gauge_bytes(kLinkF64R12, V) : 0);
-    if (eo_request(p)) {
-        if (!eo[WD_F64]) b += 2 * gauge_bytes(lat->gauge12 ? kLinkF64R12 : WD_F64, V / 2);
-        if (prec != WD_F64 && !eo[prec]) b += 2 * gauge_bytes(prec, V / 2);
-    } else if (prec != WD_F64 && !form[prec]) {
-        b += gauge_bytes(prec, V);
+// re-read what every lattice in the ledger holds now (ledger_mu held)
+static void refresh_ledger(wd_server *s, wd_lattice *also) {
+    std::vector<const void *> keys;
+    s->ledger.lattices(&keys);
+    if (also && std::find(keys.begin(), keys.end(), (const void *)also) == keys.end())
+        keys.push_back(also);
+    for (const void *k : keys) {
+        size_t master = 0, derived[kNumDerived];
+        lattice_forms((wd_lattice *)k, &master, derived);
+        s->ledger.observe(k, master, derived);
     }
-    return b;
-}
-
-static size_t lattice_gauge_charge(const wd_lattice *lat, const wd_solve_params &p) {
-    const bool none[3] = {false, false, false};
-    return gauge_need(lat, p, none, none);
-}
-
-// extra gauge bytes admitting request p on lat would add
-static size_t gauge_extra(wd_server *s, wd_lattice *lat, const wd_solve_params &p) {
-    auto it = s->lat_use.find(lat);
-    if (it == s->lat_use.end()) return lattice_gauge_charge(lat, p);
-    return gauge_need(lat, p, it->second.form, it->second.eo);
 }
 
 // have_info: the solve ran to completion and its device status is valid
 static void finish_request(wd_server *s, const std::shared_ptr<Request> &r, int rc,
                            bool have_info) {
-    r->t_done = now_seconds();
-    r->rc = rc;
-    r->info.assign(r->p.nrhs, wd_solve_info{});
-    if (have_info) r->solve->info(r->info.data());
-    for (auto &i : r->info) {
-        i.seconds = r->t_done - r->t_submit;
+    const double t_done = now_seconds();
+    std::vector<wd_solve_info> info(r->p.nrhs, wd_solve_info{});
+    if (have_info) r->solve->info(info.data());
+    for (auto &i : info) {
+        i.seconds = t_done - r->t_submit;
         i.queued_seconds = r->t_admit > 0 ? r->t_admit - r->t_submit : i.seconds;
         if (!have_info) i.status = rc;
     }
     r->solve.reset();  // stream-ordered release of the workspace
-    s->used -= r->charged;
-    auto &lu = s->lat_use[r->lat];
-    if (--lu.users == 0) {
-        s->used -= lu.charged;
-        s->lat_use.erase(r->lat);
+    {
+        std::lock_guard<std::mutex> lk(s->ledger_mu);
+        if (r->t_admit > 0) s->ledger.retire(r->lat, r->need.workspace);
     }
-    r->lat->users.fetch_sub(1);
     if (r->slot >= 0) s->slot_busy[r->slot] = 0;
-    r->state = 2;
-    s->latencies.push_back(r->t_done - r->t_submit);
-    s->t_last = r->t_done;
+    {
+        std::lock_guard<std::mutex> lk(s->stat_mu);
+        s->latencies.push_back(t_done - r->t_submit);
+        s->t_last = t_done;
+    }
+    // the lattice is free for the caller once the result is visible (and
+    // may then be destroyed: nothing below touches it)
+    r->lat->users.fetch_sub(1);
+    s->book.publish(r, [&](Request &q) {
+        q.rc = rc;
+        q.info = std::move(info);
+    });
+}
+
+// admit queued requests in arrival order while the budget and the slots allow
+static void admit(wd_server *s) {
+    while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
+        auto r = s->queue.front();
+        {
+            std::lock_guard<std::mutex> lk(s->ledger_mu);
+            refresh_ledger(s, r->lat);
+            std::vector<Eviction> ev;
+            if (!s->ledger.plan(r->lat, r->need, &ev)) return;  // head of line waits
+            for (const Eviction &e : ev) {
+                release_form((wd_lattice *)e.lat, e.form);
+                s->ledger.evicted(e.lat, e.form);
+            }
+            s->ledger.admit(r->lat, r->need);
+        }
+        s->queue.pop_front();
+        int slot = 0;
+        while (s->slot_busy[slot]) ++slot;
+        s->slot_busy[slot] = 1;
+        r->slot = slot;
+        r->t_admit = now_seconds();
+        r->solve.reset(new Solve(r->lat, r->p, r->b, r->x));
+        int rc = r->solve->setup(s->streams[slot], &s->slots[slot]);
+        if (rc == WD_OK && s->cfg.chunk_iters > 0) r->solve->set_chunk(s->cfg.chunk_iters);
+        if (rc == WD_OK) rc = r->solve->start();
+        {
+            // the forms the setup built, as the lattice holds them
+            std::lock_guard<std::mutex> lk(s->ledger_mu);
+            refresh_ledger(s, nullptr);
+        }
+        if (rc != WD_OK) {
+            finish_request(s, r, rc, false);
+            continue;
+        }
+        s->active.push_back(r);
+    }
 }
 
 static void scheduler(wd_server *s) {
     (void)hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // admit in arrival order while budget and slots allow
-        while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
-            auto r = s->reqs[s->queue.front()];
-            const size_t extra = gauge_extra(s, r->lat, r->p);
-            const size_t need = request_bytes(r->lat, r->p) + extra;
-            if (s->used + need > s->cfg.hbm_budget_bytes) break;  // head of line waits
-            s->queue.pop_front();
-            int slot = 0;
-            while (s->slot_busy[slot]) ++slot;
-            s->slot_busy[slot] = 1;
-            r->slot = slot;
-            r->charged = request_bytes(r->lat, r->p);
-            auto &lu = s->lat_use[r->lat];
-            lu.users += 1;
-            lu.charged += extra;
-            lu.form[WD_F64] = true;
-            if (eo_request(r->p)) {
-                lu.eo[WD_F64] = true;
-                lu.eo[r->p.prec_inner] = true;
-            } else {
-                lu.form[r->p.prec_inner] = true;
-            }
-            s->used += r->charged + extra;
-            s->peak = std::max(s->peak, s->used);
-            r->t_admit = now_seconds();
-            r->state = 1;
-            r->solve.reset(new Solve(r->lat, r->p, r->b, r->x));
-            int rc = r->solve->setup(s->streams[slot], &s->slots[slot]);
-            if (rc == WD_OK && s->cfg.chunk_iters > 0) r->solve->set_chunk(s->cfg.chunk_iters);
-            if (rc == WD_OK) rc = r->solve->start();
-            if (rc != WD_OK) {
-                finish_request(s, r, rc, false);
-                continue;
-            }
-            s->active.push_back(r);
-        }
-        if (s->active.empty()) {
-            if (s->stopping && s->queue.empty()) break;
-            s->cv.wait_for(lk, std::chrono::milliseconds(2));
-            continue;
-        }
+        std::vector<std::shared_ptr<Request>> fresh;
+        const bool idle = s->active.empty();
+        const bool open = s->book.take(&fresh, idle, std::chrono::milliseconds(2));
+        for (auto &r : fresh) s->queue.push_back(r);
+        if (!open && s->queue.empty() && s->active.empty()) break;
+        admit(s);
+        if (s->active.empty()) continue;
         // one non-blocking turn over the running requests
         bool progressed = false;
         for (size_t k = 0; k < s->active.size();) {
@@ -193,11 +200,15 @@ static void scheduler(wd_server *s) {
                 finish_request(s, r, r->solve->result(), true);
             s->active.erase(s->active.begin() + k);
         }
-        if (!progressed) {
-            lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(50));
-            lk.lock();
-        }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+void servers_forget(wd_lattice *lat) {
+    std::lock_guard<std::mutex> g(g_servers_mu);
+    for (wd_server *s : g_servers) {
+        std::lock_guard<std::mutex> lk(s->ledger_mu);
+        s->ledger.forget(lat);
     }
 }
 
@@ -210,9 +221,16 @@ extern "C" {
 int wd_server_create(const wd_server_config *cfg, wd_server **out) {
     if (!cfg || !out) return fail(WD_ERR_ARG, "null argument");
     if (cfg->hbm_budget_bytes == 0) return fail(WD_ERR_ARG, "hbm_budget_bytes must be > 0");
+    if (cfg->n_streams < 0 || (cfg->n_streams > 0 && !cfg->streams))
+        return fail(WD_ERR_ARG, "n_streams = %d with %s stream array", (int)cfg->n_streams,
+                    cfg->streams ? "a" : "no");
+    if (cfg->n_streams > 64) return fail(WD_ERR_ARG, "at most 64 caller streams");
     wd_server *s = new (std::nothrow) wd_server();
     if (!s) return fail(WD_ERR_NOMEM, "host allocation failed");
     s->cfg = *cfg;
+    s->ledger = Ledger(cfg->hbm_budget_bytes);
+    s->own_streams = cfg->n_streams == 0;
+    if (!s->own_streams) s->cfg.max_active = cfg->n_streams;
     if (s->cfg.max_active <= 0) s->cfg.max_active = 8;
     if (s->cfg.max_active > 64) s->cfg.max_active = 64;
     (void)hipGetDevice(&s->device);
@@ -220,18 +238,15 @@ int wd_server_create(const wd_server_config *cfg, wd_server **out) {
     s->slots.assign(s->cfg.max_active, SlotRes{});
     s->slot_busy.assign(s->cfg.max_active, 0);
     for (int i = 0; i < s->cfg.max_active; ++i) {
-        if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
-            for (int j = 0; j < i; ++j) {
-                (void)hipStreamDestroy(s->streams[j]);
-                s->slots[j].destroy();
-            }
-            delete s;
-            return fail(WD_ERR_HIP, "hipStreamCreate failed");
-        }
-        int rc = s->slots[i].create();
+        int rc = WD_OK;
+        if (!s->own_streams)
+            s->streams[i] = (hipStream_t)cfg->streams[i];
+        else if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess)
+            rc = fail(WD_ERR_HIP, "hipStreamCreate failed");
+        if (rc == WD_OK) rc = s->slots[i].create();
         if (rc) {
             for (int j = 0; j <= i; ++j) {
-                (void)hipStreamDestroy(s->streams[j]);
+                if (s->own_streams && s->streams[j]) (void)hipStreamDestroy(s->streams[j]);
                 s->slots[j].destroy();
             }
             delete s;
@@ -239,6 +254,10 @@ int wd_server_create(const wd_server_config *cfg, wd_server **out) {
         }
     }
     s->t_start = now_seconds();
+    {
+        std::lock_guard<std::mutex> g(g_servers_mu);
+        g_servers.insert(s);
+    }
     s->thr = std::thread(scheduler, s);
     *out = s;
     return WD_OK;
@@ -251,48 +270,56 @@ int wd_submit(wd_server *s, wd_lattice *lat, const wd_solve_params *p, const dou
     if (rc) return rc;
     if (!b || !x) return fail(WD_ERR_ARG, "null argument");
     if (b == x) return fail(WD_ERR_ARG, "b and x must not overlap");
-    const size_t need = request_bytes(lat, *p) + lattice_gauge_charge(lat, *p);
-    if (need > s->cfg.hbm_budget_bytes)
-        return fail(WD_ERR_NOMEM, "request needs %zu bytes, more than the whole budget (%zu)",
-                    need, s->cfg.hbm_budget_bytes);
     auto r = std::make_shared<Request>();
+    r->need = request_need(lat, *p);
+    // the request alone on an empty server: workspace, float64 links, forms
+    size_t master = 0, derived[kNumDerived];
+    lattice_forms(lat, &master, derived);
+    size_t alone = r->need.workspace + master;
+    for (int f = 0; f < kNumDerived; ++f) alone += r->need.form_bytes[f];
+    if (alone > s->cfg.hbm_budget_bytes)
+        return fail(WD_ERR_NOMEM, "request needs %zu bytes, more than the whole budget (%zu)",
+                    alone, s->cfg.hbm_budget_bytes);
     r->lat = lat;
     r->p = *p;
     r->b = b;
     r->x = x;
     r->t_submit = now_seconds();
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stopping) return fail(WD_ERR_STATE, "server is shutting down");
-        r->ticket = s->next_ticket++;
-        lat->users.fetch_add(1);
-        s->reqs[r->ticket] = r;
-        s->queue.push_back(r->ticket);
-        *ticket = r->ticket;
+    lat->users.fetch_add(1);
+    const uint64_t t = s->book.submit(r);
+    if (!t) {
+        lat->users.fetch_sub(1);
+        return fail(WD_ERR_STATE, "server is shutting down");
     }
-    s->cv.notify_one();
+    *ticket = t;
     return WD_OK;
 }
 
 int wd_poll(wd_server *s, uint64_t ticket, wd_solve_info *info) {
     if (!s) return fail(WD_ERR_ARG, "null server");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return fail(WD_ERR_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-    const auto &r = it->second;
-    if (r->state != 2) return WD_PENDING;
-    if (info)
-        for (int k = 0; k < r->p.nrhs; ++k) info[k] = r->info[k];
-    if (r->rc < 0) fail(r->rc, "request %llu failed", (unsigned long long)ticket);
-    return r->rc;
+    int rc = WD_PENDING;
+    const int st = s->book.poll(ticket, [&](const Request &r) {
+        if (info)
+            for (int k = 0; k < r.p.nrhs; ++k) info[k] = r.info[k];
+        rc = r.rc;
+    });
+    if (st < 0)
+        return fail(WD_ERR_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (st == 0) return WD_PENDING;
+    if (rc < 0) fail(rc, "request %llu failed", (unsigned long long)ticket);
+    return rc;
 }
 
 int wd_server_stats(wd_server *s, double *solves_per_s, double *p50_s, double *p99_s) {
     if (!s || !solves_per_s || !p50_s || !p99_s) return fail(WD_ERR_ARG, "null argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    std::vector<double> l = s->latencies;
+    std::vector<double> l;
+    double span = 0.0;
+    {
+        std::lock_guard<std::mutex> lk(s->stat_mu);
+        l = s->latencies;
+        span = (s->t_last > s->t_start) ? s->t_last - s->t_start : 0.0;
+    }
     const size_t n = l.size();
-    const double span = (s->t_last > s->t_start) ? s->t_last - s->t_start : 0.0;
     *solves_per_s = span > 0 ? (double)n / span : 0.0;
     if (n == 0) {
         *p50_s = *p99_s = 0.0;
@@ -313,22 +340,22 @@ int wd_server_stats(wd_server *s, double *solves_per_s, double *p50_s, double *p
 
 int wd_server_peak_bytes(wd_server *s, size_t *bytes) {
     if (!s || !bytes) return fail(WD_ERR_ARG, "null argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    *bytes = s->peak;
+    std::lock_guard<std::mutex> lk(s->ledger_mu);
+    *bytes = s->ledger.peak();
     return WD_OK;
 }
 
 int wd_server_destroy(wd_server *s) {
     if (!s) return fail(WD_ERR_ARG, "null server");
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stopping = true;
-    }
-    s->cv.notify_one();
+    s->book.stop();
     if (s->thr.joinable()) s->thr.join();
+    {
+        std::lock_guard<std::mutex> g(g_servers_mu);
+        g_servers.erase(s);
+    }
     for (size_t i = 0; i < s->streams.size(); ++i) {
         (void)hipStreamSynchronize(s->streams[i]);
-        (void)hipStreamDestroy(s->streams[i]);
+        if (s->own_streams) (void)hipStreamDestroy(s->streams[i]);
         s->slots[i].destroy();
     }
     delete s;

@@ -123,7 +123,7 @@ size_t Solve::footprint(const wd_lattice *lat, const wd_solve_params &p) {
     const bool eo = (p.form & WD_SOLVE_EVEN_ODD) != 0;
     const int V = eo ? lat->g.V / 2 : lat->g.V, nr = p.nrhs;
     const int lo = p.prec_inner;
-    const int lo_xr = lo == WD_F16 ? WD_F32 : lo;
+    const int lo_xr = xr_prec_of(lo);
     // float64: b, b', x, r, t, Ax (+ b_o and an odd temporary for even-odd)
     size_t b = (eo ? 8 : 6) * field_bytes(WD_F64, V, nr);
     // inner: x, r in lo_xr; p, t (+ Ap unless the iteration is fused, + an
@@ -179,7 +179,7 @@ int Solve::setup(hipStream_t stream, SlotRes *res) {
         bo64_ = next(WD_F64);
         tmp64_ = next(WD_F64);
     }
-    const int lo_xr = prec_ == WD_F16 ? WD_F32 : prec_;
+    const int lo_xr = xr_prec_of(prec_);
     fuse_xr_ = fused_iteration(lat_, p_);
     xl_ = next(lo_xr);
     rl_ = next(lo_xr);

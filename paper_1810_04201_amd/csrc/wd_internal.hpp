@@ -48,11 +48,25 @@ namespace wd {
 //          F64-12: 24 planes of double2 (plane 6 mu + k: entry k of rows 0
 //                  and 1); kept beside F64-18 when every link is special
 //                  unitary to rounding
+//          F16-8:  4 planes of 8 halves (plane mu; the 8-real form of
+//                  Link<kLinkF16R8>), in place of F16-12 on lattices
+//                  created with WD_F16_LINKS_8
 // Row 2 of the 12-real forms is rebuilt as conj(row0 x row1), which is exact
 // for special unitary links; the antiperiodic boundary sign is therefore
 // never folded into stored links but applied to the hop result.
 
 constexpr int kNComp = 12;  // 4 spins x 3 colours
+
+// Precision of the inner solver's x and r beside binary16 p and t: float32,
+// or (WD_F16_XR16=1) binary16 with a site scale like p.  Float64 and float32
+// inner solves keep x and r in their own precision.
+#ifndef WD_F16_XR16
+#define WD_F16_XR16 0
+#endif
+constexpr int kF16XrPrec = WD_F16_XR16 ? WD_F16 : WD_F32;
+__host__ __device__ constexpr int xr_prec_of(int prec) {
+    return prec == WD_F16 ? kF16XrPrec : prec;
+}
 constexpr int kTile = 64;   // entries per tile
 
 __host__ __device__ inline size_t tiles_of(int64_t n) { return (size_t)((n + kTile - 1) / kTile); }
@@ -66,14 +80,21 @@ inline size_t spinor_bytes(int prec, int64_t n) { return tiles_of(n) * spinor_ti
 // link form of float64 links stored as 12 reals (the other forms are named
 // by their precision)
 constexpr int kLinkF64R12 = 3;
+// link form of binary16 links stored as 8 reals (lattice flag
+// WD_F16_LINKS_8), in place of the 12-real binary16 form
+constexpr int kLinkF16R8 = 4;
 // largest |row 2 - conj(row 0 x row 1)| of a link that may be stored as 12
 // reals: a few hundred times the rounding of a special unitary matrix
 constexpr double kSu3Tol = 1e-14;
 
 inline size_t gauge_tile_bytes(int form) {
-    return form == WD_F64 ? 36u * 1024u
-                          : (form == WD_F32 ? 12u * 1024u
-                                            : (form == WD_F16 ? 12u * 512u : 24u * 1024u));
+    switch (form) {
+        case WD_F64: return 36u * 1024u;
+        case WD_F32: return 12u * 1024u;
+        case WD_F16: return 12u * 512u;
+        case kLinkF16R8: return 4u * 1024u;
+        default: return 24u * 1024u;  // kLinkF64R12
+    }
 }
 
 inline size_t gauge_bytes(int prec, int64_t V) { return tiles_of(V) * gauge_tile_bytes(prec); }
@@ -82,10 +103,17 @@ struct Geom {
     int L[4];  // Lx, Ly, Lz, Lt
     int V;
     int antiperiodic;
+    int f16_links8;     // binary16 links in the 8-real form (host-side choice)
     int tx, ty, tz;     // brick extents (divisors of Lx, Ly, Lz)
     int ncx, ncy, ncz;  // Lx / tx, Ly / ty, Lz / tz
     int bvol;           // tx * ty * tz
 };
+
+// storage form of a lattice's links for a precision (the float64 12-real
+// form is chosen separately, where the links are special unitary)
+inline int link_form(const Geom &g, int prec) {
+    return prec == WD_F16 && g.f16_links8 ? kLinkF16R8 : prec;
+}
 
 // internal site index -> lattice coordinates
 __host__ __device__ inline void coords_of(const Geom &g, int i, int &x, int &y, int &z, int &t) {
@@ -345,7 +373,14 @@ inline bool tm_eligible(const Geom &g) { return g.bvol % 64 == 0; }
 // float kernels run four waves per SIMD and do best with at most 256.
 inline int part_sites(int n, int prec) {
     if (prec == WD_F64 && n % 192 == 0) return 192;
-    const int cap = prec == WD_F64 ? 384 : 256;
+    // WD_PART_CAP overrides the float kernels' cap (tuning; at most the
+    // marching stencil's largest workgroup)
+    static const int lo_cap = [] {
+        const char *e = getenv("WD_PART_CAP");
+        const int v = e ? atoi(e) : 0;
+        return v >= 64 && v <= kTmMaxBlock ? v : 256;
+    }();
+    const int cap = prec == WD_F64 ? 384 : lo_cap;
     if (n <= cap) return n;
     // the largest multiple of 64 within the cap that divides n
     for (int w = cap - cap % 64; w >= 64; w -= 64)

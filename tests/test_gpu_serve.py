@@ -40,9 +40,13 @@ def _lattices(env, specs):
 REQS = [  # lattice, kappa, prec, nrhs, source seed
     ("a", 0.121, "f32", 1, 1), ("b", 0.124, "f16", 3, 2), ("a", 0.118, "f64", 1, 3),
     ("c", 0.1245, "f32", 12, 4), ("b", 0.115, "f64", 2, 5), ("a", 0.123, "f16", 5, 6),
-    ("c", 0.12, "f16", 1, 7), ("b", 0.122, "f32", 1, 8),
+    ("c", 0.12, "f16", 1, 7), ("b", 0.122, "f32", 1, 8), ("d", 0.124, "f32", 2, 9),
+    ("e", 0.1245, "f16", 1, 10), ("d", 0.119, "f16", 3, 11),
 ]
-SPECS = [("a", (8, 8, 8, 8), 31), ("b", (4, 6, 8, 10), 32), ("c", (12, 12, 12, 12), 33)]
+# the serving mix's lattice sizes: 8^4, 12^4, 16^3 x 32 and 24^3 x 48 (plus a
+# lattice whose extents all differ)
+SPECS = [("a", (8, 8, 8, 8), 31), ("b", (4, 6, 8, 10), 32), ("c", (12, 12, 12, 12), 33),
+         ("d", (16, 16, 16, 32), 34), ("e", (24, 24, 24, 48), 35)]
 
 
 def _sources(torch, dev, lat, nrhs, seed):
@@ -162,3 +166,98 @@ def test_failures_stay_with_their_ticket(env):
     tiny.close()
     srv.close()
     lat.close()
+
+
+def _wait_all(srv, wd, tickets, limit=120):
+    res = {}
+    deadline = time.time() + limit
+    while len(res) < len(tickets) and time.time() < deadline:
+        for t in tickets:
+            if t not in res:
+                rc, info = srv.poll(t)
+                if rc != wd.WD_PENDING:
+                    res[t] = (rc, info)
+        time.sleep(0.002)
+    assert len(res) == len(tickets)
+    return res
+
+
+def test_budget_holds_resident_forms_of_two_lattices(env):
+    """Two 8^4 lattices alternate float32 requests under a budget with room
+    for one lattice's float64 links, one request's workspace and one and a
+    half float32 link forms.  A retired request's float32 form stays
+    allocated and charged, so before the other lattice builds its own the
+    server must release it: the two forms never coexist, the charge never
+    exceeds the budget, and every result is bitwise the one solved alone
+    (a released form is rebuilt bit for bit)."""
+    torch, dev, wd = env
+    # the same two gauge fields twice: solved alone, and served
+    ref = _lattices(env, [("a", (8, 8, 8, 8), 61), ("b", (8, 8, 8, 8), 62)])
+    lats = _lattices(env, [("a", (8, 8, 8, 8), 61), ("b", (8, 8, 8, 8), 62)])
+    V = 4096
+    master = lats["a"].gauge_bytes()  # float64 links only, right after set_gauge
+    assert master == lats["b"].gauge_bytes() == V * (576 + 384)
+    f32 = V * 192
+    # CG workspace of one float32 request on 8^4 (6 float64 fields, 4 float32
+    # fields, partial sums, solver state; each field padded by 256 bytes)
+    ws = 6 * (V * 192 + 256) + 4 * (V * 96 + 256) + 768 + 1536 + 256
+    budget = master + ws + f32 + f32 // 2
+    order = ["a", "b", "a", "b", "a", "b"]
+    srcs = [_sources(torch, dev, lats[n], 1, 70 + k) for k, n in enumerate(order)]
+    alone = []
+    for n, b in zip(order, srcs):
+        x = torch.zeros_like(b)
+        rc, _ = ref[n].solve(b, x, 0.12, tol=1e-10, prec="f32")
+        assert rc == 0
+        alone.append(x.cpu())
+    srv = wd.Server(hbm_budget_bytes=budget, max_active=4)
+    xs = [torch.full_like(b, float("nan")) for b in srcs]
+    tickets = [srv.submit(lats[n], b, x, 0.12, prec="f32") for n, b, x in zip(order, srcs, xs)]
+    res = _wait_all(srv, wd, tickets)
+    for t, x, want in zip(tickets, xs, alone):
+        rc, info = res[t]
+        assert rc == 0 and info[0]["true_rel_resid"] <= 1e-10
+        assert torch.equal(x.cpu(), want)
+    assert 0 < srv.peak_bytes() <= budget
+    # the last request ran on b: a's float32 form was released for it
+    assert lats["a"].gauge_bytes() == master
+    assert lats["b"].gauge_bytes() == master + f32
+    srv.close()
+    for lat in list(lats.values()) + list(ref.values()):
+        lat.close()
+
+
+def test_server_on_caller_streams(env):
+    """wd_server_config.streams: the slots run on the caller's torch streams
+    (two of them, so two requests at a time); results are bitwise the ones
+    solved alone, and the streams stay usable after the server is gone."""
+    torch, dev, wd = env
+    lats = _lattices(env, [("a", (8, 8, 8, 8), 81), ("b", (4, 6, 8, 10), 82)])
+    reqs = [("a", "f32", 1, 1), ("b", "f16", 2, 2), ("a", "f64", 1, 3), ("b", "f32", 3, 4)]
+    alone = []
+    for n, prec, nrhs, seed in reqs:
+        b = _sources(torch, dev, lats[n], nrhs, seed)
+        x = torch.zeros_like(b)
+        rc, _ = lats[n].solve(b, x, 0.124, tol=1e-10, prec=prec, nrhs=nrhs)
+        assert rc == 0
+        alone.append(x.cpu())
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    srv = wd.Server(hbm_budget_bytes=4 << 30, streams=streams)
+    xs, tickets = [], []
+    for n, prec, nrhs, seed in reqs:
+        b = _sources(torch, dev, lats[n], nrhs, seed)
+        x = torch.full_like(b, float("nan"))
+        tickets.append(srv.submit(lats[n], b, x, 0.124, tol=1e-10, prec=prec, nrhs=nrhs))
+        xs.append((b, x))
+    res = _wait_all(srv, wd, tickets)
+    srv.close()
+    for t, (b, x), want in zip(tickets, xs, alone):
+        assert res[t][0] == 0
+        assert torch.equal(x.cpu(), want)
+    for s in streams:
+        with torch.cuda.stream(s):
+            y = torch.ones(16, device=dev) * 2
+        s.synchronize()
+        assert float(y.sum()) == 32.0
+    for lat in lats.values():
+        lat.close()
