@@ -167,6 +167,22 @@ int wd_apply_schur(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs
 int wd_apply(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs, const double *in,
              double *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): wd_apply
+ * with no allocation.  The two internal-layout fields wd_apply allocates
+ * live instead in a fixed 128 MiB scratch array that the library holds on
+ * each GPU it runs on until the process ends; the call makes no hipMalloc,
+ * hipFree or allocating library call.  2 * (internal field bytes of nrhs
+ * spinors on V sites) must fit the scratch (e.g. float64 with V * nrhs up to
+ * 349,525 sites), else WD_ERR_ARG; the lattice's link form for `prec` must
+ * already be resident (float64 always is; float32 and binary16 forms are
+ * built by the first wd_apply or solve in that precision), else
+ * WD_ERR_STATE.  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on a GPU (different streams, or threads) race.  Stream-ordered;
+ * same arguments and results as wd_apply. */
+int wd_apply_noalloc(wd_lattice *lat, double kappa, int prec, int dagger, int nrhs,
+                     const double *in, double *out, void *stream);
+
 /* --------------------------------------------------- fields (internal layout)
  * A wd_field holds nrhs spinors in the layout the kernels use: sites in
  * brick-column order (bricks of the lattice, each column marching in t),

@@ -94,6 +94,7 @@ _SIGS = {
     "wd_apply_Ddag": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp],
     "wd_apply": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
     "wd_apply_schur": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
+    "wd_apply_noalloc": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp, _vp, _vp],
     "wd_set_halo_gauge": [_vp, _vp, _vp],
     "wd_halo_pack": [_vp, _i32, _vp, _vp, _vp, _vp],
     "wd_dslash_halo": [_vp, ctypes.c_double, _i32, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp],
