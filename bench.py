@@ -80,11 +80,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--only", choices=["multi_rhs", "small_configs", "serving", "slab_share"],
+                    help="run one of the extra workloads alone and print its JSON (profiling)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="STATS_CSV")
     ap.add_argument("--valu-summary", metavar="PMC_CSV")
     ap.add_argument("--out")
     ap.add_argument("--cmd", default="")
+    ap.add_argument("--match", default="", help="--trace-summary: only kernels matching")
     return ap.parse_args()
 
 
@@ -147,6 +150,13 @@ def main():
 
     if args.probe:
         return probe(np, torch, synth, wd)
+    if args.only:
+        fn = {"multi_rhs": lambda: multi_rhs(np, torch, synth, wd),
+              "small_configs": lambda: small_configs(np, torch, synth, wd),
+              "serving": lambda: serving(np, torch, synth, wd, args.serve_requests),
+              "slab_share": lambda: slab_share(np, torch, synth, wd)}[args.only]
+        print(json.dumps({args.only: fn()}))
+        return
 
     dims = tuple(int(v) for v in args.dims.split("x"))
     V = int(np.prod(dims))
@@ -234,6 +244,7 @@ def main():
         bps = XR_BYTES_PER_SITE[prec] if key.startswith("xr_") else BYTES_PER_SITE[prec]
         achieved = V * bps / (avg_ms * 1e-3) / 1e9
         traffic = load_traffic(key) if full else None
+        mix = "probe_4r1w" if key.startswith("xr_") else "probe_3r1w"
         return {
             "kernel": what,
             "bound": "hbm",
@@ -248,8 +259,11 @@ def main():
             "launches": apps[key],
             "bytes_per_site": bps,
             "sites_per_launch": V,
-            "copy_GBps": round(copy_gbs["probe"], 1),
+            "copy_GBps": copy_gbs["probe"],
             "frac_of_copy": round(achieved / copy_gbs["probe"], 4),
+            # the probe with the kernel's own read/write mix
+            "stream_GBps": copy_gbs[mix],
+            "frac_of_stream": round(achieved / copy_gbs[mix], 4),
         }
 
     plain = roof("f64", f"dslash_f64 (k_dslash_tm<F64>, time-marching stencil, "
@@ -344,15 +358,18 @@ def main():
 
 
 def copy_bandwidth(torch, wd):
-    """Streaming ceilings, median of 5 (read + write bytes over the kernel
-    time, HIP events): the library's streaming copy probe (wd_stream_copy,
-    16-byte non-temporal loads and stores) on 2 GiB, the reference for the
-    stencils' rates next to the 8 TB/s peak; torch's device copy beside it."""
-    n = 256 * 1024 * 1024
-    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
-    b = torch.empty_like(a)
+    """Streaming ceilings, median of 5 (bytes read plus written over the kernel
+    time, HIP events), from the library's streaming probe (wd_stream_probe,
+    16-byte non-temporal loads and stores) on 1 GiB arrays: a copy (1 read
+    per write), the stencil's mix (3 reads per write: 576 / 192 bytes per
+    site) and the r-updating stencil's (4 per write: 768 / 192); torch's
+    device copy beside them."""
+    n = 128 * 1024 * 1024
+    src = [torch.full((n,), float(k + 1), dtype=torch.float64, device="cuda:0")
+           for k in range(4)]
+    b = torch.empty_like(src[0])
 
-    def med(fn):
+    def med(fn, nread):
         for _ in range(2):
             fn()
         ts = []
@@ -364,17 +381,20 @@ def copy_bandwidth(torch, wd):
             e1.record()
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
-        return 2 * n * 8 / statistics.median(ts) / 1e6
+        return round((nread + 1) * n * 8 / statistics.median(ts) / 1e6, 1)
 
-    res = {"probe": med(lambda: wd.wd_stream_copy(a, b)), "torch_copy": med(lambda: b.copy_(a)),
-           "bytes": 2 * n * 8, "peak": HBM_PEAK_GBS}
-    assert torch.equal(a, b)
-    res["probe_frac_of_peak"] = round(res["probe"] / HBM_PEAK_GBS, 4)
-    res["probe"] = round(res["probe"], 1)
-    res["torch_copy"] = round(res["torch_copy"], 1)
-    del a, b
+    res = {"probe": med(lambda: wd.wd_stream_probe(src[:1], b), 1)}
+    assert torch.equal(b, src[0])
+    res["probe_3r1w"] = med(lambda: wd.wd_stream_probe(src[:3], b), 3)
+    assert float(b[0]) == 6.0
+    res["probe_4r1w"] = med(lambda: wd.wd_stream_probe(src, b), 4)
+    res["torch_copy"] = med(lambda: b.copy_(src[0]), 1)
+    res.update({"array_bytes": n * 8, "peak": HBM_PEAK_GBS})
+    for k in ("probe", "probe_3r1w", "probe_4r1w"):
+        res[k + "_frac_of_peak"] = round(res[k] / HBM_PEAK_GBS, 4)
+    del src, b
     torch.cuda.empty_cache()
-    log(f"copy: {res}")
+    log(f"streaming ceilings: {res}")
     return res
 
 
@@ -1059,6 +1079,8 @@ def trace_summary(args):
     converged return at once and would dilute the plain average."""
     with open(args.trace_summary) as f:
         rows = list(csv.DictReader(f))
+    if args.match:
+        rows = [r for r in rows if re.search(args.match, r["Name"])]
     rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
     busy = {}
     tr = args.trace_summary.replace("_kernel_stats.csv", "_kernel_trace.csv")

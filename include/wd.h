@@ -359,13 +359,16 @@ int wd_server_destroy(wd_server *s);
  * until the next call on this thread). */
 const char *wd_last_error(void);
 
-/* Streaming probe for measurement: dst = src, `bytes` (a multiple of 16;
- * both device pointers 16-byte aligned, not overlapping) moved with 16-byte
+/* Streaming probe for measurement: dst = the element-wise sum (as float64)
+ * of nsrc (1..4) device arrays of `bytes` bytes each (a multiple of 16; all
+ * pointers 16-byte aligned; no source overlapping dst), moved with 16-byte
  * non-temporal loads and stores, the access pattern of the solver's vector
- * kernels.  Its rate (bytes read plus bytes written over the kernel time) is
- * the device's practical streaming ceiling, beside the published HBM peak,
- * for comparing the stencils' rates.  Stream-ordered. */
-int wd_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+ * kernels.  nsrc reads per write reproduce a kernel's read/write mix (1 is a
+ * copy; 3 matches the stencil, 4 the r-updating stencil), and the rate (bytes
+ * read plus written over the kernel time) is the device's practical
+ * streaming ceiling for that mix, beside the published HBM peak.
+ * Stream-ordered. */
+int wd_stream_probe(const void *const *src, int nsrc, void *dst, size_t bytes, void *stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * stencil launch.  wd_timing_read returns the summed milliseconds and launch

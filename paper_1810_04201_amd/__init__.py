@@ -113,7 +113,7 @@ _SIGS = {
                         ctypes.POINTER(ctypes.c_double)],
     "wd_server_peak_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "wd_server_destroy": [_vp],
-    "wd_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
+    "wd_stream_probe": [ctypes.POINTER(_vp), _i32, _vp, ctypes.c_size_t, _vp],
     "wd_last_error": [],
     "wd_timing_enable": [_i32],
     "wd_timing_reset": [],
@@ -281,16 +281,16 @@ def wd_cg_solve(h, params: wd_solve_params, b, x, volume, stream=None):
     return rc, [i.as_dict() for i in infos]
 
 
-def wd_stream_copy(src, dst, stream=None):
-    """dst = src through the library's streaming probe kernel (any dtype;
-    contiguous device tensors of the same byte size, a multiple of 16)."""
-    nb = src.numel() * src.element_size()
-    if dst.numel() * dst.element_size() != nb:
-        raise ValueError("src and dst sizes differ")
-    for t in (src, dst):
-        if not (t.is_cuda and t.is_contiguous()):
-            raise ValueError("src and dst must be contiguous device tensors")
-    _check(lib.wd_stream_copy(_vp(src.data_ptr()), _vp(dst.data_ptr()), nb, _stream(stream)))
+def wd_stream_probe(srcs, dst, stream=None):
+    """dst = the element-wise sum of the tensors in srcs (1..4 contiguous
+    float64 device tensors of dst's size) through the library's streaming
+    probe kernel."""
+    nb = dst.numel() * dst.element_size()
+    for t in list(srcs) + [dst]:
+        if not (t.is_cuda and t.is_contiguous()) or t.numel() * t.element_size() != nb:
+            raise ValueError("sources and dst must be contiguous device tensors of one size")
+    arr = (_vp * len(srcs))(*[s.data_ptr() for s in srcs])
+    _check(lib.wd_stream_probe(arr, len(srcs), _vp(dst.data_ptr()), nb, _stream(stream)))
 
 
 def wd_timing_enable(on=True):

@@ -311,7 +311,11 @@ struct Link<WD_F16> {
 // separate instruction on it):
 //   dot2_pp(a, b, c) = a.x b.x + a.y b.y + c     dot2_pm = a.x b.x - a.y b.y + c
 //   dot2_mp          = -a.x b.x + a.y b.y + c    dot2_mm = -a.x b.x - a.y b.y + c
-// The *0 forms start a chain at c = 0.
+// The *0 forms start a chain at c = 0.  A dot product's result may be read
+// by the next dot product of a chain as its accumulator at once, but by any
+// other vector instruction only after three wait states; the compiler does
+// not see inside the asm, so the *_e forms, which end a chain and whose
+// results other instructions read, wait those states themselves.
 #define WD_DOT2(NAME, MODS)                                                                 \
     __device__ __forceinline__ float NAME(h2_t a, h2_t b, float c) {                        \
         float d;                                                                            \
@@ -322,6 +326,13 @@ struct Link<WD_F16> {
         float d;                                                                            \
         asm("v_dot2_f32_f16 %0, %1, %2, 0" MODS : "=v"(d) : "v"(a), "v"(b));                \
         return d;                                                                           \
+    }                                                                                       \
+    __device__ __forceinline__ float NAME##_e(h2_t a, h2_t b, float c) {                    \
+        float d;                                                                            \
+        asm("v_dot2_f32_f16 %0, %1, %2, %3" MODS "\n\ts_nop 2"                              \
+            : "=v"(d)                                                                       \
+            : "v"(a), "v"(b), "v"(c));                                                      \
+        return d;                                                                           \
     }
 WD_DOT2(dot2_pp, "")
 WD_DOT2(dot2_pm, " neg_hi:[0,1,0]")
@@ -330,16 +341,6 @@ WD_DOT2(dot2_mm, " neg_lo:[0,1,0] neg_hi:[0,1,0]")
 #undef WD_DOT2
 
 __device__ __forceinline__ h2_t h2_swap(h2_t b) { return __builtin_shufflevector(b, b, 1, 0); }
-
-// the sign modifiers of the dot products (WD_H2_MODS 1), or explicit
-// negated / swapped operand pairs and the plain instruction (0)
-#ifndef WD_H2_MODS
-#define WD_H2_MODS 0
-#endif
-
-__device__ __forceinline__ float dot2(h2_t a, h2_t b, float c) {
-    return __builtin_amdgcn_fdot2(a, b, c, false);
-}
 
 template <bool NT>
 __device__ __forceinline__ void Link<WD_F16>::load_h2(const void *g, int mu, int s, h2_t u[9]) {
@@ -351,36 +352,16 @@ __device__ __forceinline__ void Link<WD_F16>::load_h2(const void *g, int mu, int
     }
     // row 2 = conj(u0[j1] u1[j2] - u0[j2] u1[j1]): re(ab - cd) = a.b(-) - c.d(-),
     // im(ab - cd) = a.swap(b) - c.swap(d)
-#if WD_H2_MODS
     h2_t s1[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) s1[j] = h2_swap(u[3 + j]);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        const float re = dot2_pm(u[j1], u[3 + j2], dot2_mp0(u[j2], u[3 + j1]));
-        const float im = dot2_pp(u[j1], s1[j2], dot2_mm0(u[j2], s1[j1]));
+        const float re = dot2_pm_e(u[j1], u[3 + j2], dot2_mp0(u[j2], u[3 + j1]));
+        const float im = dot2_pp_e(u[j1], s1[j2], dot2_mm0(u[j2], s1[j1]));
         u[6 + j] = h2_t{(_Float16)re, (_Float16)(-im)};
     }
-#else
-    // operand pairs of the row-1 entries: (x, -y), (y, x), (-x, y), (-y, -x)
-    h2_t bc[3], bs[3], dn[3], dsn[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const h2_t b = u[3 + j];
-        bc[j] = h2_t{b.x, -b.y};
-        bs[j] = h2_t{b.y, b.x};
-        dn[j] = h2_t{-b.x, b.y};
-        dsn[j] = h2_t{-b.y, -b.x};
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        const float re = dot2(u[j1], bc[j2], dot2(u[j2], dn[j1], 0.f));
-        const float im = dot2(u[j1], bs[j2], dot2(u[j2], dsn[j1], 0.f));
-        u[6 + j] = h2_t{(_Float16)re, (_Float16)(-im)};
-    }
-#endif
 }
 
 // (1 + S gamma_mu) psi on packed halves: the two upper spin components
@@ -412,7 +393,6 @@ __device__ __forceinline__ void project_h2(const h2_t p[12], h2_t h0[3], h2_t h1
 //   U^dag h: re = U.x h.x + U.y h.y,  im = U.x h.y - U.y h.x = U . swap(h)(-)
 template <bool ADJ>
 __device__ __forceinline__ void su3_mul_h2(const h2_t u[9], const h2_t h[3], cx<float> w[3]) {
-#if WD_H2_MODS
     h2_t hs[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) hs[b] = h2_swap(h[b]);
@@ -422,32 +402,14 @@ __device__ __forceinline__ void su3_mul_h2(const h2_t u[9], const h2_t h[3], cx<
                    m2 = ADJ ? u[6 + a] : u[3 * a + 2];
         float re, im;
         if (ADJ) {
-            re = dot2_pp(m2, h[2], dot2_pp(m1, h[1], dot2_pp0(m0, h[0])));
-            im = dot2_pm(m2, hs[2], dot2_pm(m1, hs[1], dot2_pm0(m0, hs[0])));
+            re = dot2_pp_e(m2, h[2], dot2_pp(m1, h[1], dot2_pp0(m0, h[0])));
+            im = dot2_pm_e(m2, hs[2], dot2_pm(m1, hs[1], dot2_pm0(m0, hs[0])));
         } else {
-            re = dot2_pm(m2, h[2], dot2_pm(m1, h[1], dot2_pm0(m0, h[0])));
-            im = dot2_pp(m2, hs[2], dot2_pp(m1, hs[1], dot2_pp0(m0, hs[0])));
+            re = dot2_pm_e(m2, h[2], dot2_pm(m1, h[1], dot2_pm0(m0, h[0])));
+            im = dot2_pp_e(m2, hs[2], dot2_pp(m1, hs[1], dot2_pp0(m0, hs[0])));
         }
         w[a] = {re, im};
     }
-#else
-    // operand pairs: U h takes (h.x, -h.y) and (h.y, h.x); U^dag h takes h
-    // itself and (h.y, -h.x)
-    h2_t hr[3], hi[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        hr[b] = ADJ ? h[b] : h2_t{h[b].x, -h[b].y};
-        hi[b] = ADJ ? h2_t{h[b].y, -h[b].x} : h2_t{h[b].y, h[b].x};
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const h2_t m0 = ADJ ? u[a] : u[3 * a], m1 = ADJ ? u[3 + a] : u[3 * a + 1],
-                   m2 = ADJ ? u[6 + a] : u[3 * a + 2];
-        const float re = dot2(m2, hr[2], dot2(m1, hr[1], dot2(m0, hr[0], 0.f)));
-        const float im = dot2(m2, hi[2], dot2(m1, hi[1], dot2(m0, hi[0], 0.f)));
-        w[a] = {re, im};
-    }
-#endif
 }
 
 // acc += s * (the hop result rebuilt to four spins), as accumulate(), with

@@ -50,9 +50,10 @@
 #define WD_NT_OUT 1
 #endif
 // binary16 hops (12-real links) with their link products on packed halves
-// (v_dot2_f32_f16) instead of float32 operands
+// (v_dot2_f32_f16) instead of float32 operands: 48^3 x 96 binary16 stencil
+// 0.63 -> 0.56 ms, its r-updating form 0.82 -> 0.79 ms
 #ifndef WD_F16_DOT2
-#define WD_F16_DOT2 0
+#define WD_F16_DOT2 1
 #endif
 // the marching stencil's fused r update: load r at the start of the step
 // (its latency hidden behind the hops) instead of after them; per
