@@ -4,21 +4,24 @@ eps = 0.3, Gaussian source), on one MI355X.
 
 One step = gauge ingest (canonical -> packed forms) + the plain FP64 CG solve
 + the mixed-precision solve (FP16-12 inner, FP64 reliable updates) of the
-same source, every kernel in libwdirac.  `value` is the whole-step stencil
-throughput: stencil applications x V x 1320 flop over the step wall time.
-The JSON line also carries the time to solution of each solver, the FP64
-stencil's roofline (HIP events recorded on its launch stream, traffic from
-the committed counter summary when it matches the current kernel source),
-the stencil alone per precision, a device copy as the practical streaming
-ceiling, the 4^4 and 16^3 x 32 configurations, the 12-source batched solve
-on 24^3 x 48, Poisson request streams through the solve server, and the CPU
-oracle's stencil throughput (and its 4^4 CG time).  Inputs are synthetic and
-resident in HBM before timing.
+same source, every kernel in libwdirac.  `value` is the FP64 stencil's
+throughput inside the FP64 solve: 1320 flop x V over its average launch
+time (HIP events recorded on its launch stream in an instrumented re-run of
+the step).  The JSON line also carries the time to solution of each solver
+from the timed region, the dominant kernel's roofline (traffic from the
+committed counter summary when it matches the current kernel source), the
+stencil alone per precision, streaming ceilings (the library's probe with
+the stencils' read/write mix, and torch's device copy), the 4^4 and
+16^3 x 32 configurations, the 12-source batched solve on 24^3 x 48, Poisson
+request streams through the solve server, and the CPU oracle on a sample of
+the same workload.  Inputs are synthetic and resident in HBM before timing.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
     python bench.py --probe                  # workload for rocprofv3 counter runs
     python bench.py --pmc-summary FETCH.csv WRITE.csv --out profiles/X.json --cmd "..."
-    python bench.py --trace-summary STATS.csv --out profiles/X.md --cmd "..."
+    python bench.py --trace-summary STATS.csv --out profiles/X.md --cmd "..." [--match RE]
+    python bench.py --valu-summary PMC.csv --out profiles/X.md --cmd "..."
+    python bench.py --only multi_rhs         # one extra workload alone (profiling)
 """
 from __future__ import annotations
 
@@ -1049,8 +1052,8 @@ def valu_summary(args):
     lines = ["# Vector-ALU work of the stencil launches", "", f"Command: `{args.cmd}`", "",
              "Issue time: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz), the least time "
              "the chip needs to issue the launch's vector instructions; the launch durations "
-             "are in the kernel statistics and the bench line (e.g. FP64 stencil 1.93 ms, "
-             "binary16 0.65 ms, the 12-source FP32 stencil 0.57 ms).", "",
+             "are in the kernel statistics and the bench line (e.g. FP64 stencil 1.86 ms, "
+             "binary16 0.55 ms, the 12-source FP32 stencil 0.54 ms).", "",
              "| kernel | launch shape (threads) | VALU wave-instr. | issue time ms |",
              "|---|---|---|---|"]
     # per kernel and launch shape, the launch that did the most work (a
