@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--probe-multi", action="store_true",
+                    help="workload for counter runs of the 12-source batch (24^3 x 48)")
+    ap.add_argument("--multi-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "TRACE_CSV"))
     ap.add_argument("--only", choices=["multi_rhs", "small_configs", "serving", "slab_share"],
                     help="run one of the extra workloads alone and print its JSON (profiling)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
@@ -140,6 +143,8 @@ def main():
         return trace_summary(args)
     if args.valu_summary:
         return valu_summary(args)
+    if args.multi_summary:
+        return multi_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                           "(no collective exchange is built; one GPU's share of a t-slab "
@@ -153,6 +158,8 @@ def main():
 
     if args.probe:
         return probe(np, torch, synth, wd)
+    if args.probe_multi:
+        return probe_multi(np, torch, synth, wd)
     if args.only:
         fn = {"multi_rhs": lambda: multi_rhs(np, torch, synth, wd),
               "small_configs": lambda: small_configs(np, torch, synth, wd),
@@ -925,6 +932,138 @@ def probe(np, torch, synth, wd):
     fb.close()
     lat.close()
     print("probe nrhs=12 done", flush=True)
+
+
+MULTI_DIMS = (24, 24, 24, 48)
+
+
+def probe_multi(np, torch, synth, wd):
+    """Workload for counter and trace runs of the 12-source batch on 24^3 x 48
+    (FP32-12): one source, then all 12, each as five stencil sweeps and six
+    eager CG iterations (FP32 inner).  A tiny streaming-probe launch marks
+    the start and end of each phase in the dispatch order."""
+    dev = torch.device("cuda:0")
+    dims = MULTI_DIMS
+    lat = wd.Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.gauge(dims, 4, synth.EXP, 0.3)).to(dev))
+    B = torch.from_numpy(synth.gaussian_sources(dims, list(range(200, 212)))).to(dev)
+    tick_src = torch.zeros(4096, dtype=torch.float64, device=dev)
+    tick_dst = torch.empty_like(tick_src)
+    os.environ["WD_GRAPH"] = "0"
+
+    def marker():
+        torch.cuda.synchronize()
+        wd.wd_stream_probe([tick_src], tick_dst)
+        torch.cuda.synchronize()
+
+    for nrhs in (1, 12):
+        marker()
+        src = B[:nrhs].contiguous() if nrhs > 1 else B[0].contiguous()
+        fa = wd.Field(lat, "f32", nrhs=nrhs)
+        fb = wd.Field(lat, "f32", nrhs=nrhs)
+        fa.load(src)
+        for _ in range(5):
+            wd.wd_dslash(lat, 0.124, 0, fa, fb)
+        torch.cuda.synchronize()
+        fa.close()
+        fb.close()
+        x = torch.zeros_like(src)
+        lat.solve(src, x, 0.124, tol=1e-10, prec="f32", nrhs=nrhs, max_iter=6)
+        torch.cuda.synchronize()
+        print(f"probe-multi nrhs={nrhs} done", flush=True)
+    marker()
+    lat.close()
+
+
+def multi_summary(args):
+    """Per-kernel time and HBM traffic of --probe-multi, one source against
+    twelve: time per launch from a kernel trace, FETCH_SIZE / WRITE_SIZE per
+    launch from two counter runs (scaled as the stencil summary is), both as
+    per-rhs-site figures."""
+    fetch = _pmc_rows(args.multi_summary[0])
+    write = _pmc_rows(args.multi_summary[1])
+    # fetch/write factors of this chip's counters (2 GiB copies calibrate the
+    # stencil summary; the same factors hold here)
+    try:
+        with open(TRAFFIC_FILE) as f:
+            cal = json.load(f)["copy_calibration"]
+        ff, wf = cal["fetch_factor"], cal["write_factor"]
+    except (OSError, ValueError, KeyError):
+        ff, wf = 2.0, 1.0
+    trace = []
+    with open(args.multi_summary[2]) as f:
+        for r in csv.DictReader(f):
+            trace.append({"id": int(r["Dispatch_Id"]), "name": r["Kernel_Name"],
+                          "grid": int(r["Grid_Size"]) if "Grid_Size" in r else
+                          int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]),
+                          "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+    trace.sort(key=lambda r: r["id"])
+
+    def phases(rows):
+        """rows between the probe's markers: [nrhs 1 rows, nrhs 12 rows]"""
+        cut = [k for k, r in enumerate(rows) if "k_stream_probe" in r["name"]]
+        return [rows[cut[0] + 1:cut[1]], rows[cut[1] + 1:cut[2]]]
+
+    V = 1
+    for d in MULTI_DIMS:
+        V *= d
+    short = lambda n: re.sub(r"\(.*", "", n.replace("void ", "")).replace("wd::", "")
+    lines = ["# 12-source batch against one source: kernel time and HBM traffic (24^3 x 48, FP32-12)",
+             "", f"Command: `{args.cmd}`", "",
+             "Per launch: median over the launches of the phase that did work; bytes are "
+             "FETCH_SIZE and WRITE_SIZE scaled by the copy calibration "
+             f"(x{ff} and x{wf}), per rhs-site (V = {V} sites).", "",
+             "| kernel | nrhs | launches | us per launch | us per rhs | fetch B/rhs-site | "
+             "write B/rhs-site | TB/s |", "|---|---|---|---|---|---|---|---|"]
+    per_iter = {}
+    for nrhs, fr, wr, tr in zip((1, 12), phases(fetch), phases(write), phases(trace)):
+        groups = {}
+        for r in tr:
+            groups.setdefault((r["name"], r["grid"]), {"ns": [], "f": [], "w": []})["ns"].append(r["ns"])
+        for r in fr:
+            g = groups.get((r["name"], r["grid"]))
+            if g is not None:
+                g["f"].append(r.get("FETCH_SIZE", 0.0))
+        for r in wr:
+            g = groups.get((r["name"], r["grid"]))
+            if g is not None:
+                g["w"].append(r.get("WRITE_SIZE", 0.0))
+        rows = []
+        for (name, grid), g in groups.items():
+            m = max(g["ns"])
+            ns = statistics.median(d for d in g["ns"] if d > 0.5 * m)
+            if ns < 2000:
+                continue  # finalizers, status copies
+            # launches enqueued past the iteration limit return at once
+            fk = statistics.median(v for v in g["f"] if v >= 0.5 * max(g["f"])) if g["f"] else 0.0
+            wk = statistics.median(v for v in g["w"] if v >= 0.5 * max(g["w"])) if g["w"] else 0.0
+            fb, wb = fk * 1024 * ff, wk * 1024 * wf
+            rows.append((short(name), len(g["ns"]), ns, fb, wb))
+        rows.sort(key=lambda r: -r[2])
+        for name, n, ns, fb, wb in rows:
+            lines.append(f"| `{name}` | {nrhs} | {n} | {ns / 1e3:.1f} | {ns / 1e3 / nrhs:.1f} | "
+                         f"{fb / (V * nrhs):.0f} | {wb / (V * nrhs):.0f} | "
+                         f"{(fb + wb) / ns / 1e3:.2f} |")
+        # one inner CG iteration: the reducing stencil (q = D p), the
+        # r-updating one and the x/p update
+        pats = (r"k_dslash_tm<1, false, true, \d+, false, false, 1>",
+                r"k_dslash_tm<1, true, true, \d+, false, true, 1>", r"k_update_xp<1, 1>")
+        it = [r for r in rows if any(re.fullmatch(p, r[0]) for p in pats)]
+        if len(it) == 3:
+            ns = sum(r[2] for r in it)
+            b = sum(r[3] + r[4] for r in it)
+            per_iter[nrhs] = (ns / nrhs, b / (V * nrhs), b / ns / 1e3)
+    lines += ["", "One inner CG iteration (reducing stencil + r-updating stencil + x/p update):", "",
+              "| nrhs | us per rhs | bytes per rhs-site | TB/s |", "|---|---|---|---|"]
+    for nrhs, (us, bps, tbs) in sorted(per_iter.items()):
+        lines.append(f"| {nrhs} | {us / 1e3:.1f} | {bps:.0f} | {tbs:.2f} |")
+    if 1 in per_iter and 12 in per_iter:
+        lines += ["", f"Batch speed-up per iteration: {per_iter[1][0] / per_iter[12][0]:.3f}; "
+                  f"bytes per rhs-site {per_iter[12][1] / per_iter[1][1]:.3f} of one source's, "
+                  f"streamed at {per_iter[12][2] / per_iter[1][2]:.3f} of its rate."]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def _pmc_rows(path):
