@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="STATS_CSV")
     ap.add_argument("--valu-summary", metavar="PMC_CSV")
+    ap.add_argument("--sq-summary", nargs="+", metavar="PMC_CSV",
+                    help="wave occupancy and wait counters of the probe's stencil launches")
     ap.add_argument("--out")
     ap.add_argument("--cmd", default="")
     ap.add_argument("--match", default="", help="--trace-summary: only kernels matching")
@@ -145,6 +147,8 @@ def main():
         return valu_summary(args)
     if args.multi_summary:
         return multi_summary(args)
+    if args.sq_summary:
+        return sq_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                           "(no collective exchange is built; one GPU's share of a t-slab "
@@ -1209,6 +1213,52 @@ def valu_summary(args):
         name = r["name"].split("(")[0].replace("void wd::", "")
         lines.append(f"| `{name}` | {r['grid']} | {valu / 1e6:.1f} M | "
                      f"{valu * 4 / (1024 * 2.4e9) * 1e3:.3f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def sq_summary(args):
+    """Wave counters of the probe's stencil launches, from one or more
+    counter runs of `bench.py --probe` (each run holds a few SQ counters; the
+    k-th launch of a kernel is the same launch in every run).  Per kernel and
+    launch shape, the launch with the most wave-cycles: waves, their average
+    lifetime, and the share of that lifetime spent issuing (any, vector ALU,
+    vector memory) and waiting (for any instruction's dependencies)."""
+    merged = {}
+    for path in args.sq_summary:
+        seen = {}
+        for r in _pmc_rows(path):
+            if "k_dslash_tm" not in r["name"] and "k_hop_half" not in r["name"]:
+                continue
+            key = (r["name"], r["grid"])
+            k = seen.get(key, 0)
+            seen[key] = k + 1
+            e = merged.setdefault((key, k), {"name": r["name"], "grid": r["grid"]})
+            e.update({c: v for c, v in r.items() if c.startswith("SQ_")})
+    best = {}
+    for (key, _), e in merged.items():
+        if e.get("SQ_WAVE_CYCLES", 0.0) >= best.get(key, {}).get("SQ_WAVE_CYCLES", -1.0):
+            best[key] = e
+    cols = [("SQ_ACTIVE_INST_ANY", "issuing"), ("SQ_ACTIVE_INST_VALU", "VALU"),
+            ("SQ_ACTIVE_INST_VMEM", "VMEM"), ("SQ_WAIT_INST_ANY", "waiting"),
+            ("SQ_WAIT_ANY", "wait (any)")]
+    lines = ["# Wave counters of the stencil launches", "", f"Command: `{args.cmd}`", "",
+             "Shares are of SQ_WAVE_CYCLES (the waves' summed lifetime, same units): "
+             "issuing = SQ_ACTIVE_INST_ANY, VALU = SQ_ACTIVE_INST_VALU, VMEM = "
+             "SQ_ACTIVE_INST_VMEM, waiting = SQ_WAIT_INST_ANY (a wave held by an "
+             "instruction dependency, e.g. a memory wait), wait (any) = SQ_WAIT_ANY.", "",
+             "| kernel | threads | SQ_WAVES | wave-cycles per wave | SQ_BUSY_CYCLES | " +
+             " | ".join(h for _, h in cols) + " |",
+             "|---|---|---|---|---|" + "---|" * len(cols)]
+    for (_, _), e in best.items():
+        wc = e.get("SQ_WAVE_CYCLES", 0.0)
+        nw = e.get("SQ_WAVES", 0.0)
+        name = e["name"].split("(")[0].replace("void wd::", "")
+        share = [f"{e[c] / wc:.2f}" if c in e and wc > 0 else "" for c, _ in cols]
+        lines.append(f"| `{name}` | {e['grid']} | {nw:.0f} | "
+                     f"{wc / nw if nw else 0:.0f} | {e.get('SQ_BUSY_CYCLES', 0.0):.0f} | " +
+                     " | ".join(share) + " |")
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
