@@ -188,8 +188,10 @@ static hipEvent_t take_event() {
         g_evpool.pop_back();
         return e;
     }
+    // timing only: no system-scope release at the record, so the bracket
+    // holds the kernel and not a cache write-back for host visibility
     hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
+    (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
 }
 
