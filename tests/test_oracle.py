@@ -218,6 +218,42 @@ def test_gauge_covariance(dagger):
     assert rel(lhs, rhs) < 1e-14
 
 
+def _shift4(a, dims, s):
+    """Canonical field moved by s = (sx, sy, sz, st): out(x + s) = a(x)."""
+    Lx, Ly, Lz, Lt = dims
+    f = a.reshape((Lt, Lz, Ly, Lx) + a.shape[1:])
+    f = np.roll(f, (s[3], s[2], s[1], s[0]), axis=(0, 1, 2, 3))
+    return np.ascontiguousarray(f.reshape(a.shape))
+
+
+@pytest.mark.parametrize("s", [(1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1),
+                               (3, 2, 5, 7)])
+@pytest.mark.parametrize("anti", [False, True])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_translation_covariance(s, anti, dagger):
+    # The lattice is periodic in x, y, z, so shifting links and source shifts
+    # D psi.  An antiperiodic t boundary is a sign on the links that cross
+    # t = T-1 -> 0; after a t shift by s_t it sits on the links leaving
+    # t = s_t - 1, and the +-1 gauge rotation g(t) = -1 for t < s_t moves it
+    # back: D[U'] (g psi') = g (D[U] psi)'.  A misplaced or doubled boundary
+    # sign breaks this.
+    dims = (4, 6, 8, 10)
+    U = synth.gauge(dims, 47, synth.EXP)
+    psi = synth.gaussian_spinor(dims, 48)
+    k = 0.125
+    f = wilson.apply_Ddag if dagger else wilson.apply_D
+    Us, ps = _shift4(U, dims, s), _shift4(psi, dims, s)
+    t = np.array([wilson.coords(x, dims)[3] for x in range(psi.shape[0])])
+    g = np.where(anti & (t < s[3]), -1.0, 1.0)[:, None, None, None]
+    lhs = f(Us, g * ps, dims, k, antiperiodic_t=anti)
+    rhs = g * _shift4(f(U, psi, dims, k, antiperiodic_t=anti), dims, s)
+    assert rel(lhs, rhs) < 1e-15
+    if anti and s[3]:
+        # without the rotation the boundary is in the wrong place
+        assert rel(f(Us, ps, dims, k, antiperiodic_t=True),
+                   _shift4(f(U, psi, dims, k, antiperiodic_t=True), dims, s)) > 1e-3
+
+
 def test_sign_convention_equivalence():
     # D_{+kappa} = eps D_{-kappa} eps, eps(x) = (-1)^(x+y+z+t), even extents
     dims = (4, 2, 6, 4)

@@ -28,7 +28,7 @@ def _hop(mutation):
             Umu = U4[..., mu, :, :]
             fwd = np.roll(psi4, -1, axis=ax)
             if mu == 3 and antiperiodic_t and mutation != "no_antiperiodic":
-                fwd[nT - 1] *= -1.0
+                fwd[0 if mutation == "boundary_at_t0" else nT - 1] *= -1.0
             if mutation == "transposed_link":
                 Uf = np.einsum("...ba,...sb->...sa", Umu, fwd)
             else:
@@ -37,8 +37,9 @@ def _hop(mutation):
             Ub = np.roll(Umu, +1, axis=ax) if mutation == "shifted_back_link" else Umu
             w = np.einsum("...ba,...sb->...sa", Ub.conj(), psi4)
             bwd = np.roll(w, +1, axis=ax)
-            if mu == 3 and antiperiodic_t and mutation != "no_antiperiodic":
-                bwd[0] *= -1.0
+            if mu == 3 and antiperiodic_t and mutation not in ("no_antiperiodic",
+                                                              "boundary_forward_only"):
+                bwd[1 if mutation == "boundary_at_t0" else 0] *= -1.0
             sgn = fwd_sign if mutation == "same_projector" else -fwd_sign
             out += np.einsum("st,...tc->...sc", IDENTITY4 + sgn * GAMMA[mu], bwd)
         return out
@@ -52,6 +53,7 @@ PINS = [
     lambda: T.test_gauge_covariance(False),
     lambda: T.test_plane_wave_eigen((4, 4, 4, 4), np.random.default_rng(1)),
     lambda: T.test_adjoint_dot_and_gamma5((4, 4, 4, 4)),
+    lambda: T.test_translation_covariance((0, 0, 0, 3), True, False),
 ]
 
 
@@ -69,10 +71,18 @@ def test_pins_pass_unmutated():
 
 
 @pytest.mark.parametrize("mutation", ["drop_direction", "no_antiperiodic", "transposed_link",
-                                      "shifted_back_link", "same_projector"])
+                                      "shifted_back_link", "same_projector", "boundary_at_t0",
+                                      "boundary_forward_only"])
 def test_stencil_mutation_caught(monkeypatch, mutation):
     monkeypatch.setattr(wilson, "hopping_4d", _hop(mutation))
     assert _some_pin_fails()
+
+
+@pytest.mark.parametrize("mutation", ["boundary_at_t0", "boundary_forward_only"])
+def test_translation_pin_alone_catches_boundary_mistakes(monkeypatch, mutation):
+    monkeypatch.setattr(wilson, "hopping_4d", _hop(mutation))
+    with pytest.raises(AssertionError):
+        T.test_translation_covariance((0, 0, 0, 3), True, False)
 
 
 def test_swapped_projectors_caught(monkeypatch):
