@@ -1276,7 +1276,14 @@ def trace_summary(args):
     rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
     busy = {}
     tr = args.trace_summary.replace("_kernel_stats.csv", "_kernel_trace.csv")
-    if os.path.exists(tr):
+    wl = os.path.join(os.path.dirname(args.trace_summary), "working_launches.json")
+    if os.path.exists(wl):
+        # the same averages, computed where the (large) trace was taken:
+        # {kernel: [calls, working launches, average ns of those]}
+        with open(wl) as f:
+            for name, (_, n, ns) in json.load(f).items():
+                busy[name] = (n, ns / 1e6)
+    elif os.path.exists(tr):
         durs = {}
         with open(tr) as f:
             for r in csv.DictReader(f):
