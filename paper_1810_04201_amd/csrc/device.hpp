@@ -401,12 +401,19 @@ __device__ __forceinline__ void su3_mul_h2(const h2_t u[9], const h2_t h[3], cx<
         const h2_t m0 = ADJ ? u[a] : u[3 * a], m1 = ADJ ? u[3 + a] : u[3 * a + 1],
                    m2 = ADJ ? u[6 + a] : u[3 * a + 2];
         float re, im;
+        // the chains without sign modifiers through the compiler's own dot
+        // product, whose wait states it places (and fills) itself
+        auto pp3 = [](h2_t x0, h2_t y0, h2_t x1, h2_t y1, h2_t x2, h2_t y2) {
+            float c = __builtin_amdgcn_fdot2(x0, y0, 0.0f, false);
+            c = __builtin_amdgcn_fdot2(x1, y1, c, false);
+            return __builtin_amdgcn_fdot2(x2, y2, c, false);
+        };
         if (ADJ) {
-            re = dot2_pp_e(m2, h[2], dot2_pp(m1, h[1], dot2_pp0(m0, h[0])));
+            re = pp3(m0, h[0], m1, h[1], m2, h[2]);
             im = dot2_pm_e(m2, hs[2], dot2_pm(m1, hs[1], dot2_pm0(m0, hs[0])));
         } else {
             re = dot2_pm_e(m2, h[2], dot2_pm(m1, h[1], dot2_pm0(m0, h[0])));
-            im = dot2_pp_e(m2, hs[2], dot2_pp(m1, hs[1], dot2_pp0(m0, hs[0])));
+            im = pp3(m0, hs[0], m1, hs[1], m2, hs[2]);
         }
         w[a] = {re, im};
     }
